@@ -1,0 +1,198 @@
+/*
+ * slimsell.h -- C ABI of the MI355X SlimSell BFS library (libslimsell.so).
+ *
+ * SlimSell BFS (Besta et al., "SlimSell: A Vectorizable Graph Representation
+ * for Breadth-First Search", arXiv 2010.09913) computes breadth-first search
+ * as one sparse-matrix dense-vector product per level over a Sell-C-sigma
+ * layout that keeps only column indices (Section III-B, "Reducing Storage
+ * Complexity with SlimSell"), under one of four semirings (Section III-A),
+ * optionally skipping finished chunks (SlimWork, Section III-C) and splitting
+ * long chunks into dynamically scheduled pieces (SlimChunk, Section III-D).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 (SS_OK) on success, a negative ss_status on failure.
+ *     slimsell_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Vertex IDs are 0-based int32 in the caller's (original) numbering.
+ *   - Pointers documented "host" are ordinary CPU memory; "device" pointers are
+ *     HIP device memory (e.g. torch CUDA tensors on ROCm).  The library never
+ *     frees memory it did not allocate.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     BFS calls enqueue work on it; argument errors are reported
+ *     synchronously, HIP errors at the call that observes them or at
+ *     slimsell_sync().
+ *   - A graph object is not safe for concurrent use: calls that use one graph
+ *     must not overlap (they share its device workspace).
+ */
+#ifndef SLIMSELL_H
+#define SLIMSELL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SS_OK = 0,
+  SS_EINVAL = -1, /* bad argument (range, null pointer, unsupported combination) */
+  SS_ENOMEM = -2, /* host or device allocation failed */
+  SS_EHIP = -3,   /* a HIP runtime call or a kernel failed */
+  SS_EUNSUP = -4, /* feature not available (e.g. no device) */
+  SS_EITER = -5   /* the level cap was reached before the BFS finished */
+} ss_status;
+
+/* The four semirings of Section III-A. */
+typedef enum {
+  SS_TROPICAL = 0, /* (min, +): frontier = distances, int32 */
+  SS_REAL = 1,     /* (+, *): fp32 frontier, binarised by the filter g */
+  SS_BOOLEAN = 2,  /* (|, &): uint8 frontier */
+  SS_SELMAX = 3    /* (max, *): int32 vertex values; yields parents directly */
+} ss_semiring;
+
+/* Chunk height.  One chunk is one 64-lane wavefront of rows. */
+#define SS_CHUNK_HEIGHT 64
+
+/* ------------------------------------------------------------------ layout */
+
+/*
+ * Host-side SlimSell layout (Section III-B; Sell-C-sigma in Section II-C):
+ *   rows are the vertices, sorted by decreasing degree inside windows of sigma
+ *   consecutive original IDs (stable on the ID), then relabelled to their
+ *   sorted position; chunk i holds rows [64 i, 64 i + 64).
+ *   col[cs[i] + 64 j + lane] is the relabelled ID of the j-th neighbour of row
+ *   64 i + lane, or -1 where the row is shorter than the chunk (padding).
+ *   The number of vertices is padded to a multiple of 64 with phantom rows
+ *   (degree 0, never reachable).
+ */
+typedef struct ss_layout ss_layout;
+
+typedef struct {
+  int32_t n;            /* vertices */
+  int32_t n_pad;        /* n rounded up to a multiple of 64 */
+  int32_t C;            /* chunk height, always 64 */
+  int32_t sigma;        /* sorting scope used */
+  int64_t n_chunks;     /* n_pad / 64 */
+  int64_t entries;      /* directed edge cells E (non-marker cells) = 2 x undirected edges */
+  int64_t cells;        /* length of col = E + padding P */
+  int32_t max_cl;       /* longest chunk, in columns (= max degree) */
+  int32_t pad0;
+  const int32_t* col;   /* [cells]   column-major per chunk, -1 = padding */
+  const int64_t* cs;    /* [n_chunks + 1] offset of chunk i in col; cs[n_chunks] = cells */
+  const int32_t* cl;    /* [n_chunks] columns of chunk i */
+  const int32_t* v;     /* [n_pad]   original ID + 1 of each row, 0 for phantom rows */
+  const int32_t* perm;  /* [n]       row of each original vertex */
+  const int32_t* degree;/* [n_pad]   degree of each row */
+} ss_layout_view;
+
+/*
+ * Build the SlimSell layout on the host from an undirected tuple list.
+ *   src, dst : host int32[m], IDs in [0, n).  Self-loops are dropped, both
+ *              directions of every tuple are kept once (duplicates dropped).
+ *   C        : must be 64.
+ *   sigma    : sorting scope; a multiple of 64 in [64, n_pad], or 1 (no sort),
+ *              or 0 meaning n_pad (sort all rows).
+ * On success *out owns host memory until slimsell_layout_free().
+ * Errors: SS_EINVAL (n < 1, m < 0, null pointer, ID out of range, bad C or
+ * sigma), SS_ENOMEM.
+ */
+int slimsell_layout_build(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                          int32_t C, int32_t sigma, ss_layout** out);
+
+/* Fill *view with pointers into the layout (valid until it is freed). */
+int slimsell_layout_view(const ss_layout* layout, ss_layout_view* view);
+
+void slimsell_layout_free(ss_layout* layout);
+
+/* ------------------------------------------------------------------- graph */
+
+/* Device-resident SlimSell graph plus its BFS workspace (opaque). */
+typedef struct ss_graph ss_graph;
+
+/*
+ * slimsell_layout_build followed by an upload to the current HIP device.
+ * Same arguments and errors, plus SS_EHIP / SS_EUNSUP when no device is usable.
+ */
+int slimsell_build(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t C,
+                   int32_t sigma, void* stream, ss_graph** out);
+
+/* Upload an existing host layout to the current device. */
+int slimsell_build_from_layout(const ss_layout* layout, void* stream, ss_graph** out);
+
+/* Size figures of a built graph (host outputs, any may be NULL). */
+int slimsell_graph_info(const ss_graph* g, int64_t* n, int64_t* entries, int64_t* padding,
+                        int64_t* chunks, int64_t* max_cl);
+
+/* Release a graph and its device memory. */
+void slimsell_free(ss_graph* g);
+
+/* ---------------------------------------------------------------------- BFS */
+
+/*
+ * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
+ *   slimwork        : 1 = skip chunks whose rows are all final (Section III-C).
+ *   split_len       : SlimChunk piece length in columns (Section III-D):
+ *                     0 = chunks are never split, >0 = split chunks longer than
+ *                     this, -1 = the graph's tuned value (see slimsell_autotune),
+ *                     falling back to the built-in default.
+ *   waves_per_group : wavefronts per workgroup (1, 2, 4, 8 or 16; 0 = default).
+ *   schedule        : 0 = fixed, 1 = learned per-level variant choice
+ *                     (slimsell_sched_load), falling back to the fixed
+ *                     heuristic when no valid model is loaded.
+ *   max_levels      : cap on SpMV iterations (0 = n + 1).  Reaching it
+ *                     returns SS_EITER.
+ *   stream          : hipStream_t.
+ *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
+ *                     (eccentricity + 1; the last one discovers nothing).
+ *   level_cap       : capacity of the two per-level arrays below.
+ *   level_ms_out    : host float[level_cap] or NULL: kernel time of each level
+ *                     of the last root, in ms (adds an event pair per level).
+ *   frontier_out    : host int64[level_cap] or NULL: vertices discovered by each
+ *                     level of the last root.
+ */
+typedef struct {
+  uint32_t size;
+  int32_t slimwork;
+  int32_t split_len;
+  int32_t waves_per_group;
+  int32_t schedule;
+  int32_t max_levels;
+  void* stream;
+  int32_t* iterations_out;
+  int32_t level_cap;
+  int32_t pad0;
+  float* level_ms_out;
+  int64_t* frontier_out;
+} ss_bfs_opts;
+
+/*
+ * BFS from each root in turn, one SpMV per level under semiring s.
+ *   roots     : host int32[num_roots], each in [0, n).
+ *   dist      : device int32[num_roots * n]; row r receives hop distances from
+ *               roots[r] (-1 = unreachable).  Required.
+ *   parent    : device int32[num_roots * n] or NULL; SS_SELMAX only (the
+ *               sel-max product yields parents: the largest-ID neighbour one
+ *               level closer; parent[root] = root; -1 = unreachable).
+ *   real_val  : device float[num_roots * n] or NULL; SS_REAL only: the
+ *               real-semiring value x_{d(v)}^v at discovery, i.e. the number
+ *               of neighbours one level closer (root 1, unreachable 0).
+ * Errors: SS_EINVAL (root out of range, parent with a non-sel-max semiring,
+ * real_val with a non-real semiring, bad options), SS_EITER, SS_EHIP.
+ */
+int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiring s,
+                 const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
+
+/* Wait for all work on `stream`; returns SS_EHIP if any of it failed. */
+int slimsell_sync(void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* slimsell_last_error(void);
+
+/* Library version string. */
+const char* slimsell_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLIMSELL_H */

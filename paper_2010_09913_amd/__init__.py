@@ -1,0 +1,189 @@
+"""MI355X SlimSell BFS: Python binding of libslimsell.so.
+
+Argument marshalling only.  The layout build runs in the library's host C++
+code and every BFS step runs in its HIP kernels; PyTorch provides device
+memory and streams.  Names follow the C ABI in include/slimsell.h.
+
+Paper: Besta et al., "SlimSell: A Vectorizable Graph Representation for
+Breadth-First Search" (arXiv 2010.09913).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _native
+from ._native import BfsOpts, LayoutView, SlimSellError, check
+
+TROPICAL, REAL, BOOLEAN, SELMAX = 0, 1, 2, 3
+SEMIRINGS = {"tropical": TROPICAL, "real": REAL, "boolean": BOOLEAN, "selmax": SELMAX}
+CHUNK = 64
+
+__all__ = ["Graph", "Layout", "layout_build", "SlimSellError", "SEMIRINGS", "TROPICAL", "REAL",
+           "BOOLEAN", "SELMAX", "version"]
+
+
+def _semiring(s) -> int:
+    if isinstance(s, str):
+        return SEMIRINGS[s]
+    return int(s)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(_native.c_i32p)
+
+
+def version() -> str:
+    return _native.load().slimsell_version().decode()
+
+
+@dataclass
+class Layout:
+    """Host copy of a SlimSell layout (see ss_layout_view in slimsell.h)."""
+    n: int
+    n_pad: int
+    sigma: int
+    n_chunks: int
+    entries: int
+    cells: int
+    max_cl: int
+    col: np.ndarray
+    cs: np.ndarray
+    cl: np.ndarray
+    v: np.ndarray
+    perm: np.ndarray
+    degree: np.ndarray
+
+    @property
+    def padding(self) -> int:
+        return self.cells - self.entries
+
+
+def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
+    """Build the SlimSell layout on the host and copy it out (no device needed)."""
+    lib = _native.load()
+    src = _i32(src)
+    dst = _i32(dst)
+    h = ctypes.c_void_p()
+    check(lib.slimsell_layout_build(_p32(src), _p32(dst), src.shape[0], n, C, sigma,
+                                    ctypes.byref(h)))
+    try:
+        v = LayoutView()
+        check(lib.slimsell_layout_view(h, ctypes.byref(v)))
+
+        def arr(ptr, count, dt):
+            if count == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+        return Layout(v.n, v.n_pad, v.sigma, v.n_chunks, v.entries, v.cells, v.max_cl,
+                      arr(v.col, v.cells, np.int32), arr(v.cs, v.n_chunks + 1, np.int64),
+                      arr(v.cl, v.n_chunks, np.int32), arr(v.v, v.n_pad, np.int32),
+                      arr(v.perm, v.n, np.int32), arr(v.degree, v.n_pad, np.int32))
+    finally:
+        lib.slimsell_layout_free(h)
+
+
+@dataclass
+class BfsResult:
+    dist: "object"             # torch int32 [num_roots, n] (device)
+    parent: "object | None"    # torch int32 [num_roots, n] (sel-max only)
+    real_val: "object | None"  # torch float32 [num_roots, n] (real only)
+    iterations: np.ndarray     # int32 [num_roots]
+    level_ms: np.ndarray | None
+    frontier: np.ndarray | None
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Graph:
+    """A SlimSell graph resident on the current HIP device."""
+
+    def __init__(self, src, dst, n: int, sigma: int = 0, stream=None):
+        lib = _native.load()
+        src = _i32(src)
+        dst = _i32(dst)
+        self._h = ctypes.c_void_p()
+        self.n = int(n)
+        self.sigma = sigma
+        st = ctypes.c_void_p() if stream is None else _stream_handle(stream)
+        check(lib.slimsell_build(_p32(src), _p32(dst), src.shape[0], n, CHUNK, sigma, st,
+                                 ctypes.byref(self._h)))
+
+    @classmethod
+    def from_edgelist(cls, g, sigma: int = 0, stream=None) -> "Graph":
+        return cls(g.src, g.dst, g.n, sigma=sigma, stream=stream)
+
+    def info(self) -> dict:
+        vals = [ctypes.c_int64() for _ in range(5)]
+        check(_native.load().slimsell_graph_info(self._h, *[ctypes.byref(x) for x in vals]))
+        n, entries, padding, chunks, max_cl = (x.value for x in vals)
+        return dict(n=n, entries=entries, padding=padding, chunks=chunks, max_cl=max_cl,
+                    cells=entries + padding)
+
+    def bfs(self, roots, semiring="selmax", *, slimwork: bool = True, split_len: int = -1,
+            waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
+            level_cap: int = 0, want_parent: bool = True, want_real: bool = True,
+            dist=None, parent=None, real_val=None) -> BfsResult:
+        """BFS from every root; outputs are device tensors in original vertex IDs."""
+        import torch
+        s = _semiring(semiring)
+        roots = _i32(np.atleast_1d(roots))
+        nr = roots.shape[0]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if dist is None:
+            dist = torch.empty((nr, self.n), dtype=torch.int32, device=dev)
+        if parent is None and want_parent and s == SELMAX:
+            parent = torch.empty((nr, self.n), dtype=torch.int32, device=dev)
+        if real_val is None and want_real and s == REAL:
+            real_val = torch.empty((nr, self.n), dtype=torch.float32, device=dev)
+        iters = np.zeros(max(nr, 1), np.int32)
+        o = BfsOpts()
+        o.size = ctypes.sizeof(BfsOpts)
+        o.slimwork = 1 if slimwork else 0
+        o.split_len = split_len
+        o.waves_per_group = waves_per_group
+        o.schedule = schedule
+        o.max_levels = max_levels
+        o.stream = _stream_handle(stream)
+        o.iterations_out = iters.ctypes.data_as(_native.c_i32p)
+        level_ms = frontier = None
+        if level_cap > 0:
+            level_ms = np.zeros(level_cap, np.float32)
+            frontier = np.zeros(level_cap, np.int64)
+            o.level_cap = level_cap
+            o.level_ms_out = level_ms.ctypes.data_as(_native.c_f32p)
+            o.frontier_out = frontier.ctypes.data_as(_native.c_i64p)
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+        check(_native.load().slimsell_bfs(self._h, _p32(roots), nr, s, ctypes.byref(o),
+                                          ptr(dist), ptr(parent), ptr(real_val)))
+        return BfsResult(dist, parent, real_val, iters[:nr].copy(), level_ms, frontier)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _native.load().slimsell_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sync(stream=None) -> None:
+    check(_native.load().slimsell_sync(_stream_handle(stream)))

@@ -1,0 +1,386 @@
+// HIP kernels of one SlimSell BFS on gfx950 (CDNA4).
+//
+// One chunk of 64 rows is one 64-lane wavefront: lane = row inside the chunk,
+// so the column-major chunk layout (Section II-C, Sell-C-sigma) turns every
+// column step into one coalesced 256-byte load of `col`.  A padding cell
+// (-1, Section III-B) exec-masks its lane: no gather, no contribution.
+//
+// Level k (k >= 1) computes x_k from the previous frontier under one semiring
+// (Section III-A), derives the new frontier and updates distances/parents in
+// the same kernel (the post-processing of the semiring listing), skips chunks
+// whose rows are all final (SlimWork, Section III-C) with one wavefront ballot,
+// and combines the pieces of split chunks (SlimChunk, Section III-D) with
+// order-independent atomics; the last piece to arrive post-processes the chunk.
+//
+// Update discipline: the gathered vector is double-buffered (Jacobi), except
+// for the tropical semiring, which keeps one distance vector and reads every
+// value written during the current level (which is exactly k) as infinity, so
+// each gather still sees f_{k-1}.  Skipped chunks write nothing: a row whose
+// whole chunk is final can only neighbour rows discovered no later than the
+// next level, whose update masks it out, so stale values there never reach a
+// row that is still undiscovered.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ss {
+
+__device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
+  return ((uint64_t)run_id << 32) | (uint32_t)level;
+}
+
+// ------------------------------------------------------------ semirings ---
+
+// Tropical (min, +), Section III-A: x_k = f_k = A' (x) f_{k-1}, A' has 1 on
+// edges, 0 on the diagonal and infinity elsewhere.  The frontier is the
+// distance vector itself.
+struct Tropical {
+  using Acc = int32_t;
+  using Val = int32_t;
+  static constexpr int kId = SS_TROPICAL;
+  __device__ static Acc identity() { return kInf; }
+  __device__ static Val load(const LevelArgs& a, int32_t c) { return a.state[c]; }
+  // 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
+  __device__ static Acc term(const LevelArgs& a, Val y) { return (y < a.level) ? y + 1 : kInf; }
+  __device__ static Acc combine(Acc x, Acc y) { return x < y ? x : y; }
+  __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
+  __device__ static void atomic_combine(int32_t* p, Acc v) {
+    if (v != kInf) atomicMin(p, v);
+  }
+  __device__ static Acc take(int32_t* p) { return atomicExch(p, kInf); }
+  // f_k^row = min(f_{k-1}^row, acc): the diagonal of A' keeps the old value
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+    int32_t own = a.state[row];
+    bool fresh = (own == kInf) && (acc != kInf);
+    if (fresh) a.state[row] = acc;
+    return fresh;
+  }
+};
+
+// Real (+, *), Section III-A: x_k = A (x) f_{k-1}; f_k = [x_k (.) g_k != 0];
+// d^row = k where the row enters the frontier.  Sums of 0/1 values of at most
+// the vertex degree are exact in fp32.
+struct Real {
+  using Acc = float;
+  using Val = float;
+  static constexpr int kId = SS_REAL;
+  __device__ static Acc identity() { return 0.0f; }
+  __device__ static Val load(const LevelArgs& a, int32_t c) {
+    return static_cast<const float*>(a.vin)[c];
+  }
+  __device__ static Acc term(const LevelArgs&, Val y) { return y; }
+  __device__ static Acc combine(Acc x, Acc y) { return x + y; }
+  __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  __device__ static void atomic_combine(int32_t* p, Acc v) {
+    if (v != 0.0f) atomicAdd(reinterpret_cast<float*>(p), v);
+  }
+  __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<float*>(p), 0.0f); }
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+    uint8_t gg = a.g[row];
+    bool fresh = (acc * (float)gg) != 0.0f;
+    static_cast<float*>(a.vout)[row] = fresh ? 1.0f : 0.0f;
+    if (fresh) {
+      a.d[row] = a.level;
+      a.g[row] = 0;
+      a.rv[row] = acc;
+    }
+    return fresh;
+  }
+};
+
+// Boolean (|, &), Section III-A: x_k = A (x) f_{k-1}; f_k = x_k & g_k.
+struct Boolean {
+  using Acc = uint32_t;
+  using Val = uint8_t;
+  static constexpr int kId = SS_BOOLEAN;
+  __device__ static Acc identity() { return 0u; }
+  __device__ static Val load(const LevelArgs& a, int32_t c) {
+    return static_cast<const uint8_t*>(a.vin)[c];
+  }
+  __device__ static Acc term(const LevelArgs&, Val y) { return (Acc)y; }
+  __device__ static Acc combine(Acc x, Acc y) { return x | y; }
+  __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  __device__ static void atomic_combine(int32_t* p, Acc v) {
+    if (v) atomicOr(reinterpret_cast<uint32_t*>(p), v);
+  }
+  __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<uint32_t*>(p), 0u); }
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+    bool fresh = (acc != 0u) && (a.g[row] != 0);
+    static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
+    if (fresh) {
+      a.d[row] = a.level;
+      a.g[row] = 0;
+    }
+    return fresh;
+  }
+};
+
+// Sel-max (max, *), Section III-A: x_k = A (x) x_{k-1};
+// p_k = p_{k-1} + NOT(p_{k-1}) (.) x_k; f_k = NOT NOT x_k minus the visited
+// set; then x_k <- NOT NOT x_k (.) v with v = original ID + 1, so the max
+// picks the largest original ID among the neighbours one level closer.
+struct SelMax {
+  using Acc = int32_t;
+  using Val = int32_t;
+  static constexpr int kId = SS_SELMAX;
+  __device__ static Acc identity() { return 0; }
+  __device__ static Val load(const LevelArgs& a, int32_t c) {
+    return static_cast<const int32_t*>(a.vin)[c];
+  }
+  __device__ static Acc term(const LevelArgs&, Val y) { return y; }
+  __device__ static Acc combine(Acc x, Acc y) { return x > y ? x : y; }
+  __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
+  __device__ static void atomic_combine(int32_t* p, Acc v) {
+    if (v != 0) atomicMax(p, v);
+  }
+  __device__ static Acc take(int32_t* p) { return atomicExch(p, 0); }
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+    int32_t pr = a.state[row];
+    bool fresh = (pr == 0) && (acc != 0);
+    if (fresh) {
+      a.state[row] = acc;
+      a.d[row] = a.level;
+    }
+    static_cast<int32_t*>(a.vout)[row] = (acc != 0) ? a.v[row] : 0;
+    return fresh;
+  }
+};
+
+// ---------------------------------------------------------- level kernel ---
+
+// Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
+// U independent streaming loads of `col`, then U exec-masked gathers.
+template <class S, int U>
+__device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, const int32_t* __restrict__ p,
+                                                 int32_t ncols, typename S::Acc acc) {
+  int32_t j = 0;
+  for (; j + U <= ncols; j += U) {
+    int32_t c[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+    typename S::Acc y[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] = (c[t] >= 0) ? S::term(a, S::load(a, c[t])) : S::identity();
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc = S::combine(acc, y[t]);
+    p += (int64_t)U * kC;
+  }
+  for (; j < ncols; ++j) {
+    int32_t c = __builtin_nontemporal_load(p);
+    if (c >= 0) acc = S::combine(acc, S::term(a, S::load(a, c)));
+    p += kC;
+  }
+  return acc;
+}
+
+template <class S>
+__device__ __forceinline__ void finish_rows(const LevelArgs& a, int32_t row, typename S::Acc acc,
+                                            int lane) {
+  bool fresh = S::post(a, row, acc);
+  uint64_t found = __ballot(fresh);
+  if (found && lane == 0) {
+    a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+    if (a.count_stats)
+      atomicAdd(&a.counts[(int64_t)a.level * kCountSlots + (blockIdx.x % kCountSlots)],
+                (int32_t)__popcll(found));
+  }
+}
+
+template <class S, int U>
+__global__ void level_kernel(LevelArgs a) {
+  const int lane = threadIdx.x & (kC - 1);
+  const int wave = threadIdx.x / kC;
+  const int waves = blockDim.x / kC;
+
+  // Stop if the previous level discovered nothing, and tell the host what the
+  // previous level found (one thread of the first workgroup).
+  if (a.level > 1) {
+    const uint64_t want = level_tag(a.run_id, a.level - 1);
+    const bool prev_found = (a.any[(a.level - 1) % kRing] == want);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      __hip_atomic_store(&a.report[(a.level - 1) % kRing], (want << 1) | (prev_found ? 1u : 0u),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (!prev_found) return;
+  }
+
+  for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < a.n_units;
+       u += (int64_t)gridDim.x * waves) {
+    const Unit w = a.units[u];
+    const bool piece = (w.c1 == w.c0 + 1);
+    for (int32_t c = w.c0; c < w.c1; ++c) {
+      const int32_t row = c * kC + lane;
+      if (a.slimwork && !__any(S::live(a, row))) continue;  // whole chunk final
+      int32_t j0 = 0, j1 = a.cl[c];
+      if (piece) { j0 = w.j0; j1 = w.j1; }
+      const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
+      typename S::Acc acc = sweep<S, U>(a, p, j1 - j0, S::identity());
+      const int32_t npieces = piece ? a.pieces[c] : 1;
+      if (npieces == 1) {
+        finish_rows<S>(a, row, acc, lane);
+      } else {
+        // SlimChunk: combine this piece, the last one to arrive post-processes
+        S::atomic_combine(&a.acc[row], acc);
+        __threadfence();
+        int last = 0;
+        if (lane == 0) last = (atomicAdd(&a.arrive[c], 1) == npieces - 1);
+        last = __shfl(last, 0);
+        if (last) {
+          __threadfence();
+          acc = S::take(&a.acc[row]);
+          if (lane == 0) a.arrive[c] = 0;
+          finish_rows<S>(a, row, acc, lane);
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------- init kernel ---
+
+// Level-0 vectors (Section III-A): tropical x_0 = f_0 = e_r-style distances,
+// real/boolean f_0 = e_r with filter g = NOT f_0, sel-max x_0 = p_0 = (r+1) e_r.
+// Phantom rows start final so SlimWork can skip them.
+template <int SEMI>
+__global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const int32_t* v,
+                            int32_t root_row, void* va, void* vb, int32_t* state, uint8_t* g,
+                            int32_t* d, float* rv, int32_t* acc, int32_t* arrive) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_chunks) arrive[r] = 0;
+  if (r >= n_pad) return;
+  const bool root = (r == root_row);
+  const bool phantom = (v[r] == 0);
+  if (SEMI == SS_TROPICAL) {
+    state[r] = root ? 0 : (phantom ? 0 : kInf);
+    acc[r] = kInf;
+    return;
+  }
+  d[r] = root ? 0 : -1;
+  g[r] = (root || phantom) ? 0 : 1;
+  if (SEMI == SS_REAL) {
+    static_cast<float*>(va)[r] = root ? 1.0f : 0.0f;
+    static_cast<float*>(vb)[r] = 0.0f;
+    rv[r] = root ? 1.0f : 0.0f;
+    reinterpret_cast<float*>(acc)[r] = 0.0f;
+  } else if (SEMI == SS_BOOLEAN) {
+    static_cast<uint8_t*>(va)[r] = root ? 1 : 0;
+    static_cast<uint8_t*>(vb)[r] = 0;
+    acc[r] = 0;
+  } else {  // SS_SELMAX
+    static_cast<int32_t*>(va)[r] = root ? v[r] : 0;
+    static_cast<int32_t*>(vb)[r] = 0;
+    state[r] = root ? v[r] : (phantom ? -1 : 0);
+    acc[r] = 0;
+  }
+}
+
+// ------------------------------------------------------- finalise kernel ---
+
+// Row order -> original IDs; infinity -> -1; 1-based parents -> 0-based.
+template <int SEMI>
+__global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* state,
+                                const int32_t* d, const float* rv, int32_t* dist, int32_t* parent,
+                                float* real_val) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int32_t row = perm[o];
+  if (SEMI == SS_TROPICAL) {
+    const int32_t f = state[row];
+    dist[o] = (f >= kInf) ? -1 : f;
+    return;
+  }
+  dist[o] = d[row];
+  if (SEMI == SS_SELMAX && parent) {
+    const int32_t pr = state[row];
+    parent[o] = (pr > 0) ? pr - 1 : -1;
+  }
+  if (SEMI == SS_REAL && real_val) real_val[o] = rv[row];
+}
+
+template <class T>
+__global__ void fill_kernel(T* p, T value, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// --------------------------------------------------------------- launchers ---
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(SS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return SS_OK;
+}
+
+static inline unsigned blocks_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row,
+                void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t work = g.n_pad > g.n_chunks ? g.n_pad : g.n_chunks;
+  const unsigned blocks = blocks_for(work, 256);
+#define SS_INIT(S)                                                                             \
+  init_kernel<S><<<blocks, 256, 0, st>>>(g.n, g.n_pad, g.n_chunks, g.d_v, root_row, ws.vec_a, \
+                                         ws.vec_b, ws.state, ws.g, ws.d, ws.rv, ws.acc,       \
+                                         ws.arrive)
+  switch (semiring) {
+    case SS_TROPICAL: SS_INIT(SS_TROPICAL); break;
+    case SS_REAL: SS_INIT(SS_REAL); break;
+    case SS_BOOLEAN: SS_INIT(SS_BOOLEAN); break;
+    case SS_SELMAX: SS_INIT(SS_SELMAX); break;
+    default: return set_error(SS_EINVAL, "unknown semiring");
+  }
+#undef SS_INIT
+  return check_launch("init_kernel");
+}
+
+template <class S>
+static void launch_level_t(int waves, unsigned grid, const LevelArgs& a, hipStream_t st) {
+  level_kernel<S, 8><<<grid, waves * kC, 0, st>>>(a);
+}
+
+int launch_level(int semiring, int waves, int64_t max_groups, const LevelArgs& a, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t groups = (a.n_units + waves - 1) / waves;
+  if (groups < 1) groups = 1;
+  if (max_groups > 0 && groups > max_groups) groups = max_groups;
+  const unsigned grid = (unsigned)groups;
+  switch (semiring) {
+    case SS_TROPICAL: launch_level_t<Tropical>(waves, grid, a, st); break;
+    case SS_REAL: launch_level_t<Real>(waves, grid, a, st); break;
+    case SS_BOOLEAN: launch_level_t<Boolean>(waves, grid, a, st); break;
+    case SS_SELMAX: launch_level_t<SelMax>(waves, grid, a, st); break;
+    default: return set_error(SS_EINVAL, "unknown semiring");
+  }
+  return check_launch("level_kernel");
+}
+
+int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,
+                    int32_t* parent, float* real_val, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned blocks = blocks_for(g.n, 256);
+#define SS_FIN(S)                                                                          \
+  finalise_kernel<S><<<blocks, 256, 0, st>>>(g.n, g.d_perm, ws.state, ws.d, ws.rv, dist, \
+                                             parent, real_val)
+  switch (semiring) {
+    case SS_TROPICAL: SS_FIN(SS_TROPICAL); break;
+    case SS_REAL: SS_FIN(SS_REAL); break;
+    case SS_BOOLEAN: SS_FIN(SS_BOOLEAN); break;
+    case SS_SELMAX: SS_FIN(SS_SELMAX); break;
+    default: return set_error(SS_EINVAL, "unknown semiring");
+  }
+#undef SS_FIN
+  return check_launch("finalise_kernel");
+}
+
+int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream) {
+  if (count <= 0) return SS_OK;
+  unsigned blocks = blocks_for(count, 256);
+  if (blocks > 4096) blocks = 4096;
+  fill_kernel<int32_t><<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(p, value, count);
+  return check_launch("fill_kernel");
+}
+
+}  // namespace ss
