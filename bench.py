@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""SlimSell BFS benchmark on one MI355X.
+
+Workload: R-MAT scale 22, edge factor 16 (a, b, c = .57, .19, .19), seed 1,
+symmetrised with self-loops and duplicates dropped; C = 64, sigma = n (full
+sort), sel-max semiring, SlimWork on, SlimChunk on; 64 roots drawn uniformly
+from the nonzero-degree vertices (seed 1002).  One step = one BFS from each of
+the 64 roots.  The graph is built and uploaded before the timed region.
+
+Printed (one JSON line): whole-job GTEPS over the timed steps, the Graph500
+harmonic mean of per-root GTEPS, the roofline of the level kernel (algorithmic
+bytes per launch from the fused per-level counters over its event-timed mean
+duration), the split-length sweep, an Erdos-Renyi graph of the same size, and
+the oracle's CPU rate on a bounded sample of roots.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
+C = 64
+
+# Bytes each processed row moves in the level post-processing and the
+# gathered-vector element size (see the byte model in the design notes).
+ROW_BYTES = {"tropical": 8, "real": 14, "boolean": 7, "selmax": 16}
+TEST_BYTES = {"tropical": 4, "real": 1, "boolean": 1, "selmax": 4}
+GATHER_BYTES = {"tropical": 4, "real": 4, "boolean": 1, "selmax": 4}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def nonempty_chunks(deg: np.ndarray, chunks: int) -> int:
+    """Chunks with at least one edge under a full sort (the ones the level
+    kernel visits and tests): rows sorted by decreasing degree."""
+    return int((np.count_nonzero(deg) + C - 1) // C)
+
+
+def algorithmic_bytes(levels: dict, r: int, iters: int, semi: str, n: int,
+                      nonempty_chunks: int) -> float:
+    """Bytes the method must move for all levels of root r."""
+    cells = levels["active_cells"][r][:iters].astype(np.float64)
+    chunks = levels["active_chunks"][r][:iters].astype(np.float64)
+    per_level = (4.0 * cells + ROW_BYTES[semi] * C * chunks + 8.0 * chunks
+                 + TEST_BYTES[semi] * C * nonempty_chunks + GATHER_BYTES[semi] * n)
+    return float(per_level.sum())
+
+
+def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=True):
+    import torch
+    # warm-up (also fixes the per-root component sizes)
+    res = None
+    for _ in range(warmup):
+        res = G.bfs(roots, semi, split_len=split)
+    torch.cuda.synchronize()
+    if res is None:
+        res = G.bfs(roots, semi, split_len=split)
+        torch.cuda.synchronize()
+    reached = (res.dist >= 0)
+    m_cc = ((reached.to(torch.int64) * deg_t[None, :]).sum(dim=1) // 2).cpu().numpy()
+    out = dict(m_cc=m_cc)
+    if count_pass:
+        cres = G.bfs(roots, semi, split_len=split, level_cap=64)
+        out["levels"] = cres.levels
+        out["iterations"] = cres.iterations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(steps):
+        r = G.bfs(roots, semi, split_len=split, timing=True)
+        runs.append(r.runs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out.update(wall=wall, runs=runs)
+    return out
+
+
+def summarise(out, roots, semi, n, nonempty_chunks, steps):
+    m_cc = out["m_cc"].astype(np.float64)
+    bfs_ms = np.stack([r["bfs_ms"] for r in out["runs"]])        # [steps, roots]
+    kern_ms = np.stack([r["kernel_ms"] for r in out["runs"]])
+    launches = np.stack([r["launches"] for r in out["runs"]])
+    teps = m_cc[None, :] / (bfs_ms * 1e-3)
+    hmean = teps.size / np.sum(1.0 / teps) / 1e9
+    whole = m_cc.sum() * steps / out["wall"] / 1e9
+    s = dict(gteps_wall=whole, gteps_hmean=hmean, ms_per_step=out["wall"] * 1e3 / steps,
+             mean_bfs_ms=float(bfs_ms.mean()), level_launches=int(launches.sum()),
+             mean_launch_ms=float(kern_ms.sum() / launches.sum()))
+    if "levels" in out:
+        iters = out["iterations"]
+        per_root = np.array([algorithmic_bytes(out["levels"], i, int(iters[i]), semi, n,
+                                               nonempty_chunks) for i in range(len(roots))])
+        bytes_per_step = per_root.sum()
+        kernel_s = kern_ms.sum() / 1e3
+        achieved = bytes_per_step * steps / kernel_s / 1e9
+        s.update(bytes_per_launch=float(bytes_per_step * steps / launches.sum()),
+                 achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
+                 cells_per_bfs=float(np.mean([out["levels"]["active_cells"][i][:iters[i]].sum()
+                                              for i in range(len(roots))])))
+    return s
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--roots", type=int, default=64)
+    ap.add_argument("--split", type=int, default=-1, help="SlimChunk split length (-1 = default)")
+    ap.add_argument("--semiring", default="selmax",
+                    choices=["tropical", "real", "boolean", "selmax"])
+    ap.add_argument("--cpu-roots", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the split sweep and ER graph")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="warm-up and timed steps only (for profiler runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import graphgen
+    import paper_2010_09913_amd as ss
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    semi = args.semiring
+
+    t = time.perf_counter()
+    e = graphgen.rmat(args.scale, 16, seed=1)
+    roots = graphgen.pick_roots(e, args.roots, seed=1002)
+    log(f"generated {e.name}: {e.m} tuples in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    G = ss.Graph.from_edgelist(e, sigma=0)
+    build_s = time.perf_counter() - t
+    info = G.info()
+    deg = G.degrees()
+    deg_t = torch.from_numpy(deg.astype(np.int64)).cuda()
+    log(f"built SlimSell layout in {build_s:.1f}s: {info}")
+    nonempty = nonempty_chunks(deg, info["chunks"])
+
+    out = run_workload(ss, G, roots, semi, args.split, args.steps, args.warmup, deg_t,
+                       count_pass=not args.only_timed)
+    s = summarise(out, roots, semi, e.n, nonempty, args.steps)
+    log(f"main: {s}")
+
+    result = {
+        "metric": "GTEPS (whole job) and % of HBM peak, SlimSell BFS, R-MAT s22",
+        "value": round(s["gteps_wall"], 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(s["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded R-MAT generator)",
+        "config": {
+            "workload": f"R-MAT scale {args.scale} ef16 (.57/.19/.19) seed 1, {semi} semiring, "
+                        f"C=64, sigma=n, SlimWork on, SlimChunk split "
+                        f"{'default' if args.split == -1 else args.split}, "
+                        f"{len(roots)} roots (seed 1002), one BFS per root per step",
+            "n": e.n, "undirected_edges": int(info["entries"] // 2),
+            "cells": int(info["cells"]), "padding": int(info["padding"]),
+            "max_degree": int(info["max_cl"]), "roots": int(len(roots)),
+            "parallelism": "single GPU",
+        },
+        "gteps_hmean": round(s["gteps_hmean"], 4),
+        "mean_bfs_ms": round(s["mean_bfs_ms"], 4),
+        "build_s": round(build_s, 2),
+    }
+    if "achieved_gbs" in s:
+        result["roofline"] = {
+            "bound": "hbm", "achieved": round(s["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(s["frac"], 4), "traffic": None,
+            "kernel": f"level_kernel<{semi}>",
+            "bytes_per_launch": round(s["bytes_per_launch"]),
+            "mean_launch_ms": round(s["mean_launch_ms"], 5),
+        }
+
+    if not args.only_timed and not args.no_extra:
+        sweep = {}
+        for split in (0, 256, 1024, 4096):
+            o2 = run_workload(ss, G, roots, semi, split, max(1, args.steps // 2), 1, deg_t)
+            s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+            sweep[str(split)] = {"gteps": round(s2["gteps_wall"], 4),
+                                 "frac": round(s2.get("frac", 0.0), 4)}
+            log(f"split {split}: {s2}")
+        result["split_sweep"] = sweep
+        G.close()
+        # Erdos-Renyi graph of the same size (mean degree 32)
+        er = graphgen.er(1 << args.scale, 16 << args.scale, seed=2)
+        er_roots = graphgen.pick_roots(er, args.roots, seed=1003)
+        Ge = ss.Graph.from_edgelist(er, sigma=0)
+        deg_e = torch.from_numpy(Ge.degrees().astype(np.int64)).cuda()
+        ne = nonempty_chunks(Ge.degrees(), Ge.info()["chunks"])
+        oe = run_workload(ss, Ge, er_roots, semi, args.split, max(1, args.steps // 2), 1, deg_e)
+        se = summarise(oe, er_roots, semi, er.n, ne, max(1, args.steps // 2))
+        log(f"er: {se}")
+        result["er_2^22_deg32"] = {"gteps": round(se["gteps_wall"], 4),
+                                   "gteps_hmean": round(se["gteps_hmean"], 4),
+                                   "frac": round(se.get("frac", 0.0), 4)}
+        Ge.close()
+
+    if not args.no_cpu and not args.only_timed:
+        import oracle
+        t = time.perf_counter()
+        g = oracle.csr_from_edgelist(e)
+        log(f"oracle CSR in {time.perf_counter() - t:.1f}s")
+        sample = roots[: args.cpu_roots]
+        rates = []
+        t_all = time.perf_counter()
+        for r in sample:
+            t = time.perf_counter()
+            d = oracle.bfs(g, int(r))
+            oracle.parents_max(g, int(r), d)
+            dt = time.perf_counter() - t
+            rates.append(oracle.component_edges(g, d) / dt)
+        cpu_s = time.perf_counter() - t_all
+        rates = np.array(rates)
+        result["cpu_baseline"] = {
+            "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
+            "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(roots)} roots: FIFO-queue BFS + max-ID parent "
+                      f"pass (the sel-max outputs), 1 thread, {cpu_s:.1f}s total",
+        }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -123,14 +123,74 @@ int slimsell_build_from_layout(const ss_layout* layout, void* stream, ss_graph**
 int slimsell_graph_info(const ss_graph* g, int64_t* n, int64_t* entries, int64_t* padding,
                         int64_t* chunks, int64_t* max_cl);
 
+/*
+ * Degree of every vertex in the canonical graph (self-loops and duplicates
+ * dropped), in original IDs: host int32[n].
+ */
+int slimsell_graph_degrees(const ss_graph* g, int32_t* degree);
+
+/*
+ * Launch configuration of the level kernel for one graph (Section III-D's
+ * SlimChunk split plus the MI355X launch shape).  BFS calls use it where
+ * ss_bfs_opts leaves a field to the graph (split_len = -1, waves_per_group = 0).
+ *   split_len       : SlimChunk piece length in columns; 0 = never split.
+ *   waves_per_group : wavefronts per workgroup: 1, 2, 4, 8 or 16.
+ *   unroll          : columns per gather block: 4, 8 or 16.
+ *   max_groups      : cap on workgroups per level launch; 0 = one wavefront
+ *                     per work unit (hardware dispatch does the balancing),
+ *                     else units are strided over the capped grid.
+ *   pack_cols       : chunks shorter than split_len are packed into runs of
+ *                     at most this many columns per work unit; 0 = one chunk
+ *                     per unit; -1 = split_len.
+ */
+typedef struct {
+  int32_t split_len;
+  int32_t waves_per_group;
+  int32_t unroll;
+  int32_t max_groups;
+  int32_t pack_cols;
+  int32_t pad0;
+} ss_tune;
+
+/* Set / read the graph's launch configuration.  SS_EINVAL on a bad field. */
+int slimsell_tune_set(ss_graph* g, const ss_tune* tune);
+int slimsell_tune_get(const ss_graph* g, ss_tune* tune);
+
 /* Release a graph and its device memory. */
 void slimsell_free(ss_graph* g);
 
 /* ---------------------------------------------------------------------- BFS */
 
+/* Per-level record (see ss_bfs_opts.flags). */
+typedef struct {
+  int64_t discovered;    /* vertices that entered the frontier at this level */
+  int64_t active_chunks; /* chunks processed, i.e. not skipped by SlimWork */
+  int64_t active_cells;  /* col cells streamed (64 x columns of the processed pieces) */
+  int64_t max_active_cl; /* longest processed chunk, in columns */
+  float ms;              /* kernel time of the level (events), 0 if not timed */
+  int32_t pad0;
+} ss_level_stats;
+
+/* Per-root record (see ss_bfs_opts.flags). */
+typedef struct {
+  int32_t iterations;    /* SpMV iterations = eccentricity + 1 */
+  int32_t launches;      /* level kernels launched, incl. look-ahead ones that exit at once */
+  float kernel_ms;       /* summed time of all those level kernels (SS_STATS_TIME) */
+  float bfs_ms;          /* init kernel start to finalise end on the stream (SS_STATS_TIME) */
+} ss_run_stats;
+
+#define SS_STATS_TIME 1     /* hipEvents around every level kernel and every BFS */
+#define SS_STATS_COUNTERS 2 /* fused per-level counters (a few atomics per wavefront) */
+
 /*
  * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
- *   slimwork        : 1 = skip chunks whose rows are all final (Section III-C).
+ *   slimwork        : 0 = every row of every chunk is computed (plain SlimSell);
+ *                     1 = skip chunks whose rows are all final (SlimWork,
+ *                     Section III-C);
+ *                     2 = SlimWork plus row-level masking: inside a processed
+ *                     chunk a row that is final issues no loads and the
+ *                     column sweep stops at the longest row still live.
+ *                     Results are identical in all three modes.
  *   split_len       : SlimChunk piece length in columns (Section III-D):
  *                     0 = chunks are never split, >0 = split chunks longer than
  *                     this, -1 = the graph's tuned value (see slimsell_autotune),
@@ -144,11 +204,14 @@ void slimsell_free(ss_graph* g);
  *   stream          : hipStream_t.
  *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
  *                     (eccentricity + 1; the last one discovers nothing).
- *   level_cap       : capacity of the two per-level arrays below.
- *   level_ms_out    : host float[level_cap] or NULL: kernel time of each level
- *                     of the last root, in ms (adds an event pair per level).
- *   frontier_out    : host int64[level_cap] or NULL: vertices discovered by each
- *                     level of the last root.
+ *   flags           : SS_STATS_TIME and/or SS_STATS_COUNTERS.
+ *   level_cap       : levels per root recorded in level_stats_out.
+ *   level_stats_out : host ss_level_stats[num_roots * level_cap] or NULL;
+ *                     entry [r * level_cap + k - 1] describes level k of root r.
+ *                     Counter fields need SS_STATS_COUNTERS, ms needs
+ *                     SS_STATS_TIME; unused entries are zeroed.
+ *   run_stats_out   : host ss_run_stats[num_roots] or NULL.
+ * Requesting any statistics makes the call wait for the stream at its end.
  */
 typedef struct {
   uint32_t size;
@@ -159,10 +222,10 @@ typedef struct {
   int32_t max_levels;
   void* stream;
   int32_t* iterations_out;
+  int32_t flags;
   int32_t level_cap;
-  int32_t pad0;
-  float* level_ms_out;
-  int64_t* frontier_out;
+  ss_level_stats* level_stats_out;
+  ss_run_stats* run_stats_out;
 } ss_bfs_opts;
 
 /*

@@ -90,14 +90,23 @@ def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
         lib.slimsell_layout_free(h)
 
 
+LEVEL_FIELDS = ("discovered", "active_chunks", "active_cells", "max_active_cl", "ms")
+RUN_FIELDS = ("iterations", "launches", "kernel_ms", "bfs_ms")
+
+
 @dataclass
 class BfsResult:
     dist: "object"             # torch int32 [num_roots, n] (device)
     parent: "object | None"    # torch int32 [num_roots, n] (sel-max only)
     real_val: "object | None"  # torch float32 [num_roots, n] (real only)
     iterations: np.ndarray     # int32 [num_roots]
-    level_ms: np.ndarray | None
-    frontier: np.ndarray | None
+    levels: dict | None = None  # field -> array [num_roots, level_cap]
+    runs: dict | None = None    # field -> array [num_roots]
+
+    @property
+    def frontier(self):
+        """Vertices discovered per level of the first root (needs counters)."""
+        return None if self.levels is None else self.levels["discovered"][0]
 
 
 def _stream_handle(stream):
@@ -132,16 +141,50 @@ class Graph:
         return dict(n=n, entries=entries, padding=padding, chunks=chunks, max_cl=max_cl,
                     cells=entries + padding)
 
-    def bfs(self, roots, semiring="selmax", *, slimwork: bool = True, split_len: int = -1,
+    def degrees(self) -> np.ndarray:
+        """Canonical degree of every vertex (original IDs)."""
+        out = np.empty(self.n, np.int32)
+        check(_native.load().slimsell_graph_degrees(self._h, _p32(out)))
+        return out
+
+    TUNE_FIELDS = ("split_len", "waves_per_group", "unroll", "max_groups", "pack_cols")
+
+    def get_tune(self) -> dict:
+        t = _native.Tune()
+        check(_native.load().slimsell_tune_get(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f in self.TUNE_FIELDS}
+
+    def set_tune(self, **kw) -> dict:
+        """Update the graph's launch configuration (fields of ss_tune)."""
+        cur = self.get_tune()
+        for k, v in kw.items():
+            if k not in cur:
+                raise KeyError(k)
+            cur[k] = int(v)
+        t = _native.Tune(**cur)
+        check(_native.load().slimsell_tune_set(self._h, ctypes.byref(t)))
+        return cur
+
+    def bfs(self, roots, semiring="selmax", *, slimwork: int = 2, split_len: int = -1,
             waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
-            level_cap: int = 0, want_parent: bool = True, want_real: bool = True,
+            level_cap: int = 0, timing: bool = False, counters: bool = None,
+            want_parent: bool = True, want_real: bool = True,
             dist=None, parent=None, real_val=None) -> BfsResult:
-        """BFS from every root; outputs are device tensors in original vertex IDs."""
+        """BFS from every root; outputs are device tensors in original vertex IDs.
+
+        level_cap > 0 records per-level statistics (fused counters unless
+        counters=False); timing=True adds event timings per level and per root.
+        """
         import torch
         s = _semiring(semiring)
         roots = _i32(np.atleast_1d(roots))
         nr = roots.shape[0]
         dev = torch.device("cuda", torch.cuda.current_device())
+        for t, dt in ((dist, torch.int32), (parent, torch.int32), (real_val, torch.float32)):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != nr * self.n):
+                raise ValueError(f"output tensors must be contiguous {dt} on the device with "
+                                 f"num_roots * n = {nr * self.n} elements")
         if dist is None:
             dist = torch.empty((nr, self.n), dtype=torch.int32, device=dev)
         if parent is None and want_parent and s == SELMAX:
@@ -151,27 +194,38 @@ class Graph:
         iters = np.zeros(max(nr, 1), np.int32)
         o = BfsOpts()
         o.size = ctypes.sizeof(BfsOpts)
-        o.slimwork = 1 if slimwork else 0
+        o.slimwork = int(slimwork)
         o.split_len = split_len
         o.waves_per_group = waves_per_group
         o.schedule = schedule
         o.max_levels = max_levels
         o.stream = _stream_handle(stream)
         o.iterations_out = iters.ctypes.data_as(_native.c_i32p)
-        level_ms = frontier = None
+        if counters is None:
+            counters = level_cap > 0
+        o.flags = (_native.SS_STATS_TIME if timing else 0) | (
+            _native.SS_STATS_COUNTERS if counters else 0)
+        lvl = runs = None
         if level_cap > 0:
-            level_ms = np.zeros(level_cap, np.float32)
-            frontier = np.zeros(level_cap, np.int64)
+            lvl = (_native.LevelStats * (nr * level_cap))()
             o.level_cap = level_cap
-            o.level_ms_out = level_ms.ctypes.data_as(_native.c_f32p)
-            o.frontier_out = frontier.ctypes.data_as(_native.c_i64p)
+            o.level_stats_out = lvl
+        if timing or level_cap > 0:
+            runs = (_native.RunStats * max(nr, 1))()
+            o.run_stats_out = runs
 
         def ptr(t):
             return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
 
         check(_native.load().slimsell_bfs(self._h, _p32(roots), nr, s, ctypes.byref(o),
                                           ptr(dist), ptr(parent), ptr(real_val)))
-        return BfsResult(dist, parent, real_val, iters[:nr].copy(), level_ms, frontier)
+        levels = run_d = None
+        if lvl is not None:
+            levels = {f: np.array([getattr(x, f) for x in lvl]).reshape(nr, level_cap)
+                      for f in LEVEL_FIELDS}
+        if runs is not None:
+            run_d = {f: np.array([getattr(runs[i], f) for i in range(nr)]) for f in RUN_FIELDS}
+        return BfsResult(dist, parent, real_val, iters[:nr].copy(), levels, run_d)
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

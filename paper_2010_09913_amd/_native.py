@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EHIP", -4:
 # Every symbol include/slimsell.h declares (checked by the tests).
 EXPORTS = [
     "slimsell_layout_build", "slimsell_layout_view", "slimsell_layout_free",
-    "slimsell_build", "slimsell_build_from_layout", "slimsell_graph_info", "slimsell_free",
+    "slimsell_build", "slimsell_build_from_layout", "slimsell_graph_info",
+    "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get", "slimsell_free",
     "slimsell_bfs", "slimsell_sync", "slimsell_last_error", "slimsell_version",
 ]
 
@@ -37,13 +38,41 @@ class LayoutView(ctypes.Structure):
     ]
 
 
+class LevelStats(ctypes.Structure):
+    _fields_ = [
+        ("discovered", ctypes.c_int64), ("active_chunks", ctypes.c_int64),
+        ("active_cells", ctypes.c_int64), ("max_active_cl", ctypes.c_int64),
+        ("ms", ctypes.c_float), ("pad0", ctypes.c_int32),
+    ]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
+        ("kernel_ms", ctypes.c_float), ("bfs_ms", ctypes.c_float),
+    ]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [
+        ("split_len", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+        ("unroll", ctypes.c_int32), ("max_groups", ctypes.c_int32),
+        ("pack_cols", ctypes.c_int32), ("pad0", ctypes.c_int32),
+    ]
+
+
+SS_STATS_TIME = 1
+SS_STATS_COUNTERS = 2
+
+
 class BfsOpts(ctypes.Structure):
     _fields_ = [
         ("size", ctypes.c_uint32), ("slimwork", ctypes.c_int32), ("split_len", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32), ("schedule", ctypes.c_int32),
         ("max_levels", ctypes.c_int32), ("stream", ctypes.c_void_p),
-        ("iterations_out", c_i32p), ("level_cap", ctypes.c_int32), ("pad0", ctypes.c_int32),
-        ("level_ms_out", c_f32p), ("frontier_out", c_i64p),
+        ("iterations_out", c_i32p), ("flags", ctypes.c_int32), ("level_cap", ctypes.c_int32),
+        ("level_stats_out", ctypes.POINTER(LevelStats)),
+        ("run_stats_out", ctypes.POINTER(RunStats)),
     ]
 
 
@@ -71,6 +100,9 @@ def load() -> ctypes.CDLL:
                                    ctypes.c_int32, vp, vpp]
     lib.slimsell_build_from_layout.argtypes = [vp, vp, vpp]
     lib.slimsell_graph_info.argtypes = [vp, c_i64p, c_i64p, c_i64p, c_i64p, c_i64p]
+    lib.slimsell_graph_degrees.argtypes = [vp, c_i32p]
+    lib.slimsell_tune_set.argtypes = [vp, ctypes.POINTER(Tune)]
+    lib.slimsell_tune_get.argtypes = [vp, ctypes.POINTER(Tune)]
     lib.slimsell_free.argtypes = [vp]
     lib.slimsell_free.restype = None
     lib.slimsell_bfs.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.c_int32,
@@ -81,7 +113,9 @@ def load() -> ctypes.CDLL:
     lib.slimsell_version.argtypes = []
     lib.slimsell_version.restype = ctypes.c_char_p
     for name in ("slimsell_layout_build", "slimsell_layout_view", "slimsell_build",
-                 "slimsell_build_from_layout", "slimsell_graph_info", "slimsell_bfs",
+                 "slimsell_build_from_layout", "slimsell_graph_info",
+                 "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get",
+                 "slimsell_bfs",
                  "slimsell_sync"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

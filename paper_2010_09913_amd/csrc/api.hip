@@ -61,11 +61,13 @@ static void release_graph(Graph* g) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(g->device);
-  void* ptrs[] = {g->d_col,     g->d_cs,   g->d_cl,    g->d_v,     g->d_perm,
+  void* ptrs[] = {g->d_col,     g->d_cs,   g->d_cl,    g->d_v,     g->d_perm, g->d_deg,
                   g->ws.vec_a,  g->ws.vec_b, g->ws.state, g->ws.g, g->ws.d,
-                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counts};
+                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (void* ev : g->ev_pool)
+    if (ev) (void)hipEventDestroy(static_cast<hipEvent_t>(ev));
   if (g->ws.h_report) (void)hipHostFree(const_cast<uint64_t*>(g->ws.h_report));
   for (auto& kv : g->units) release_units(kv.second);
   (void)hipSetDevice(prev);
@@ -140,14 +142,25 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out) {
   return SS_OK;
 }
 
-static int ensure_counts(Graph& g, int64_t cap) {
-  if (cap <= g.ws.count_cap) return SS_OK;
-  if (g.ws.counts) (void)hipFree(g.ws.counts);
-  g.ws.counts = nullptr;
-  g.ws.count_cap = 0;
-  int rc = dalloc(&g.ws.counts, cap * kCountSlots);
+static int ensure_counters(Graph& g, int64_t words) {
+  if (words <= g.ws.counter_words) return SS_OK;
+  if (g.ws.counters) (void)hipFree(g.ws.counters);
+  g.ws.counters = nullptr;
+  g.ws.counter_words = 0;
+  int rc = dalloc(&g.ws.counters, words);
   if (rc) return rc;
-  g.ws.count_cap = cap;
+  g.ws.counter_words = words;
+  return SS_OK;
+}
+
+// Events for SS_STATS_TIME come from a per-graph pool that grows on demand.
+static int pool_event(Graph& g, size_t idx, hipEvent_t* out) {
+  while (g.ev_pool.size() <= idx) {
+    hipEvent_t ev = nullptr;
+    SS_HIP(hipEventCreate(&ev));
+    g.ev_pool.push_back(ev);
+  }
+  *out = static_cast<hipEvent_t>(g.ev_pool[idx]);
   return SS_OK;
 }
 
@@ -276,6 +289,8 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
   g->max_cl = L->max_cl;
   g->h_perm = L->perm;
   g->h_cl = L->cl;
+  g->h_degree.resize((size_t)L->n);
+  for (int32_t o = 0; o < L->n; ++o) g->h_degree[o] = L->degree[L->perm[o]];
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = SS_OK;
   auto up = [&](auto** dst, const auto& vec) -> int {
@@ -294,6 +309,7 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
   if (!rc) rc = up(&g->d_cl, L->cl);
   if (!rc) rc = up(&g->d_v, L->v);
   if (!rc) rc = up(&g->d_perm, L->perm);
+  if (!rc) rc = up(&g->d_deg, L->degree);
   if (!rc) {
     hipError_t ee = hipStreamSynchronize(st);
     if (ee != hipSuccess) rc = hip_fail(ee, "upload layout");
@@ -330,6 +346,34 @@ int slimsell_graph_info(const ss_graph* g, int64_t* n, int64_t* entries, int64_t
   return SS_OK;
 }
 
+int slimsell_tune_set(ss_graph* g, const ss_tune* t) {
+  if (!g || !t) return set_error(SS_EINVAL, "NULL argument");
+  const int w = t->waves_per_group;
+  if (t->split_len < 0) return set_error(SS_EINVAL, "split_len must be >= 0");
+  if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16)
+    return set_error(SS_EINVAL, "waves_per_group must be 1, 2, 4, 8 or 16");
+  if (t->unroll != 4 && t->unroll != 8 && t->unroll != 16)
+    return set_error(SS_EINVAL, "unroll must be 4, 8 or 16");
+  if (t->max_groups < 0) return set_error(SS_EINVAL, "max_groups must be >= 0");
+  if (t->pack_cols < -1) return set_error(SS_EINVAL, "pack_cols must be >= -1");
+  std::lock_guard<std::mutex> lock(g->mu);
+  g->tune = *t;
+  g->tune.pad0 = 0;
+  return SS_OK;
+}
+
+int slimsell_tune_get(const ss_graph* g, ss_tune* t) {
+  if (!g || !t) return set_error(SS_EINVAL, "NULL argument");
+  *t = g->tune;
+  return SS_OK;
+}
+
+int slimsell_graph_degrees(const ss_graph* g, int32_t* degree) {
+  if (!g || !degree) return set_error(SS_EINVAL, "NULL argument");
+  std::memcpy(degree, g->h_degree.data(), sizeof(int32_t) * g->h_degree.size());
+  return SS_OK;
+}
+
 void slimsell_free(ss_graph* g) { release_graph(g); }
 
 int slimsell_sync(void* stream) {
@@ -351,21 +395,25 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   ss_bfs_opts def;
   std::memset(&def, 0, sizeof(def));
   def.size = sizeof(def);
-  def.slimwork = 1;
+  def.slimwork = 2;
   def.split_len = -1;
   if (!o) o = &def;
   if (o->size != sizeof(ss_bfs_opts)) return set_error(SS_EINVAL, "opts->size mismatch");
+  if (o->slimwork < 0 || o->slimwork > 2) return set_error(SS_EINVAL, "slimwork must be 0, 1 or 2");
   for (int32_t r = 0; r < num_roots; ++r)
     if (roots[r] < 0 || roots[r] >= g.n) return set_error(SS_EINVAL, "root out of range [0, n)");
-  int waves = o->waves_per_group ? o->waves_per_group : (g.tuned_waves ? g.tuned_waves : 4);
+  const int waves = o->waves_per_group ? o->waves_per_group : g.tune.waves_per_group;
   if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
     return set_error(SS_EINVAL, "waves_per_group must be 1, 2, 4, 8 or 16");
   int32_t split = o->split_len;
   if (split < -1) return set_error(SS_EINVAL, "split_len must be >= -1");
-  if (split == -1) split = (g.tuned_split >= 0) ? g.tuned_split : 1024;
-  const int32_t pack = split > 0 ? split : 0;
+  if (split == -1) split = g.tune.split_len;
+  const int32_t pack = g.tune.pack_cols < 0 ? (split > 0 ? split : 0) : g.tune.pack_cols;
+  const int unroll = g.tune.unroll;
+  const int64_t max_groups = g.tune.max_groups;
   const int64_t cap = (o->max_levels > 0) ? o->max_levels : (int64_t)g.n + 1;
   if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
+  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS)) return set_error(SS_EINVAL, "bad flags");
 
   std::lock_guard<std::mutex> lock(g.mu);
   SS_HIP(hipSetDevice(g.device));
@@ -373,38 +421,41 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   UnitList* ul = nullptr;
   int rc = get_units(g, split, pack, &ul);
   if (rc) return rc;
-  const bool want_counts = o->frontier_out && o->level_cap > 0;
-  const bool want_ms = o->level_ms_out && o->level_cap > 0;
-  if (want_counts) {
-    rc = ensure_counts(g, (int64_t)o->level_cap + 1);
+  const bool timing = (o->flags & SS_STATS_TIME) != 0;
+  const int64_t lcap = o->level_cap;
+  const bool counting = (o->flags & SS_STATS_COUNTERS) && lcap > 0 && o->level_stats_out;
+  const int64_t words_per_root = (lcap + 1) * kCountSlots * kCountFields;
+  if (counting) {
+    rc = ensure_counters(g, words_per_root * num_roots);
+    if (rc) return rc;
+    rc = launch_fill_u64(g.ws.counters, 0ull, words_per_root * num_roots, st);
     if (rc) return rc;
   }
-  std::vector<hipEvent_t> evs;
   constexpr int kLookahead = 2;
+  size_t next_ev = 0;
+  std::vector<size_t> ev_first((size_t)num_roots, 0);
+  std::vector<int32_t> launches((size_t)num_roots, 0);
+  std::vector<int32_t> iters((size_t)num_roots, 0);
 
   for (int32_t r = 0; r < num_roots; ++r) {
-    const bool last = (r == num_roots - 1);
     g.run_id = (g.run_id >= 0x7FFFFFF0u) ? 1u : g.run_id + 1;
     const uint32_t run = g.run_id;
     const int32_t root_row = g.h_perm[roots[r]];
+    ev_first[r] = next_ev;
+    if (timing) {
+      hipEvent_t ev;
+      if ((rc = pool_event(g, next_ev++, &ev))) return rc;
+      SS_HIP(hipEventRecord(ev, st));
+    }
     rc = launch_init(s, g, g.ws, root_row, st);
     if (rc) return rc;
-    if (want_counts && last) {
-      rc = launch_fill_i32(g.ws.counts, 0, g.ws.count_cap * kCountSlots, st);
-      if (rc) return rc;
-    }
-    const bool timing = want_ms && last;
-    if (timing && (int64_t)evs.size() < 2 * (int64_t)o->level_cap) {
-      evs.resize(2 * (size_t)o->level_cap, nullptr);
-      for (auto& ev : evs)
-        if (!ev) SS_HIP(hipEventCreate(&ev));
-    }
     LevelArgs a;
     std::memset(&a, 0, sizeof(a));
     a.col = g.d_col;
     a.cs = g.d_cs;
     a.cl = g.d_cl;
     a.v = g.d_v;
+    a.deg = g.d_deg;
     a.units = ul->d_units;
     a.pieces = ul->d_pieces;
     a.n_units = ul->count;
@@ -415,10 +466,11 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     a.acc = g.ws.acc;
     a.arrive = g.ws.arrive;
     a.any = g.ws.any;
-    a.counts = g.ws.counts;
+    a.counters = counting ? g.ws.counters + words_per_root * r : nullptr;
     a.report = g.ws.d_report;
     a.run_id = run;
-    a.slimwork = o->slimwork ? 1 : 0;
+    a.n_pad = (uint32_t)g.n_pad;
+    a.slimwork = o->slimwork;
 
     int32_t launched = 0;
     int32_t iterations = -1;
@@ -426,12 +478,17 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
       a.level = k;
       a.vin = (k & 1) ? g.ws.vec_a : g.ws.vec_b;
       a.vout = (k & 1) ? g.ws.vec_b : g.ws.vec_a;
-      a.count_stats = (want_counts && last && k <= o->level_cap) ? 1 : 0;
-      const bool t = timing && k <= o->level_cap;
-      if (t) SS_HIP(hipEventRecord(evs[2 * (k - 1)], st));
-      int lr = launch_level((int)s, waves, 0, a, st);
+      a.count_stats = (counting && k <= lcap) ? 1 : 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timing) {
+        int pr;
+        if ((pr = pool_event(g, next_ev++, &e0))) return pr;
+        if ((pr = pool_event(g, next_ev++, &e1))) return pr;
+        SS_HIP(hipEventRecord(e0, st));
+      }
+      int lr = launch_level((int)s, waves, unroll, max_groups, a, st);
       if (lr) return lr;
-      if (t) SS_HIP(hipEventRecord(evs[2 * (k - 1) + 1], st));
+      if (timing) SS_HIP(hipEventRecord(e1, st));
       return SS_OK;
     };
     for (int32_t j = 1;; ++j) {
@@ -451,37 +508,69 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
         return set_error(SS_EITER, "level cap reached before the BFS finished");
       }
     }
+    launches[r] = launched;
+    iters[r] = iterations;
     if (o->iterations_out) o->iterations_out[r] = iterations;
     rc = launch_finalise(s, g, g.ws, dist + (int64_t)r * g.n,
                          parent ? parent + (int64_t)r * g.n : nullptr,
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
-    if (last && (timing || want_counts)) {
-      SS_HIP(hipStreamSynchronize(st));
-      const int32_t nl = std::min<int32_t>(iterations, o->level_cap);
-      if (timing) {
-        for (int32_t k = 0; k < nl; ++k) {
-          float ms = 0.f;
-          SS_HIP(hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]));
-          o->level_ms_out[k] = ms;
-        }
-        for (int32_t k = nl; k < o->level_cap; ++k) o->level_ms_out[k] = 0.f;
+    if (timing) {
+      hipEvent_t ev;
+      if ((rc = pool_event(g, next_ev++, &ev))) return rc;
+      SS_HIP(hipEventRecord(ev, st));
+    }
+  }
+
+  const bool want_levels = o->level_stats_out && lcap > 0;
+  if (!(timing || counting || o->run_stats_out || want_levels)) return SS_OK;
+  SS_HIP(hipStreamSynchronize(st));
+  std::vector<unsigned long long> h;
+  if (counting) {
+    h.resize((size_t)(words_per_root * num_roots));
+    SS_HIP(hipMemcpy(h.data(), g.ws.counters, sizeof(unsigned long long) * h.size(),
+                     hipMemcpyDeviceToHost));
+  }
+  for (int32_t r = 0; r < num_roots; ++r) {
+    float kernel_ms = 0.f, bfs_ms = 0.f;
+    std::vector<float> lvl_ms((size_t)launches[r], 0.f);
+    if (timing) {
+      const size_t e = ev_first[r];
+      auto ev = [&](size_t i) { return static_cast<hipEvent_t>(g.ev_pool[i]); };
+      for (int32_t k = 0; k < launches[r]; ++k) {
+        float ms = 0.f;
+        SS_HIP(hipEventElapsedTime(&ms, ev(e + 1 + 2 * k), ev(e + 2 + 2 * k)));
+        lvl_ms[k] = ms;
+        kernel_ms += ms;
       }
-      if (want_counts) {
-        std::vector<int32_t> h((size_t)(nl + 1) * kCountSlots);
-        SS_HIP(hipMemcpy(h.data(), g.ws.counts, sizeof(int32_t) * h.size(),
-                         hipMemcpyDeviceToHost));
-        for (int32_t k = 0; k < o->level_cap; ++k) {
-          int64_t sum = 0;
-          if (k < nl)
-            for (int q = 0; q < kCountSlots; ++q) sum += h[(size_t)(k + 1) * kCountSlots + q];
-          o->frontier_out[k] = sum;
+      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1 + 2 * launches[r])));
+    }
+    if (o->run_stats_out) {
+      ss_run_stats& rs = o->run_stats_out[r];
+      rs.iterations = iters[r];
+      rs.launches = launches[r];
+      rs.kernel_ms = kernel_ms;
+      rs.bfs_ms = bfs_ms;
+    }
+    if (want_levels) {
+      for (int64_t k = 1; k <= lcap; ++k) {
+        ss_level_stats& ls = o->level_stats_out[r * lcap + (k - 1)];
+        std::memset(&ls, 0, sizeof(ls));
+        if (k > iters[r]) continue;
+        ls.ms = timing ? lvl_ms[k - 1] : 0.f;
+        if (counting) {
+          const unsigned long long* base = h.data() + words_per_root * r;
+          for (int q = 0; q < kCountSlots; ++q) {
+            const unsigned long long* f = base + (k * kCountSlots + q) * kCountFields;
+            ls.discovered += (int64_t)f[0];
+            ls.active_chunks += (int64_t)f[1];
+            ls.active_cells += (int64_t)f[2];
+            ls.max_active_cl = std::max<int64_t>(ls.max_active_cl, (int64_t)f[3]);
+          }
         }
       }
     }
   }
-  for (auto& ev : evs)
-    if (ev) (void)hipEventDestroy(ev);
   return SS_OK;
 }
 

@@ -62,14 +62,15 @@ struct Workspace {
   int32_t* acc = nullptr;     // SlimChunk partial combine buffer (4 B per row)
   int32_t* arrive = nullptr;  // SlimChunk arrival counters (4 B per chunk)
   uint64_t* any = nullptr;    // [kRing] per-level tag (run_id << 32 | level) if it found rows
-  int32_t* counts = nullptr;  // [count_cap * kCountSlots] discovered counts per level
-  int64_t count_cap = 0;      // levels covered by counts[]
+  unsigned long long* counters = nullptr;  // per-level counters, see LevelArgs::counters
+  int64_t counter_words = 0;               // capacity of counters[]
   // host-mapped report ring written by the GPU: (tag << 1) | found
   volatile uint64_t* h_report = nullptr;
   uint64_t* d_report = nullptr;  // device view of h_report
 };
 
-constexpr int kCountSlots = 16;
+constexpr int kCountSlots = 16;  // counter atomics are spread over this many slots
+constexpr int kCountFields = 4;  // discovered, active chunks, active columns, max active cl
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
 
 struct Graph {
@@ -82,13 +83,15 @@ struct Graph {
   int32_t* d_cl = nullptr;
   int32_t* d_v = nullptr;
   int32_t* d_perm = nullptr;
+  int32_t* d_deg = nullptr;     // degree of each row (row order)
   std::vector<int32_t> h_perm;  // row of each original vertex
   std::vector<int32_t> h_cl;    // chunk lengths (for unit decomposition)
+  std::vector<int32_t> h_degree;  // degree of each original vertex
+  std::vector<void*> ev_pool;     // hipEvent_t pool for SS_STATS_TIME
   std::map<std::pair<int32_t, int32_t>, UnitList> units;  // by (split_len, pack_cols)
   Workspace ws;
   uint32_t run_id = 0;
-  int32_t tuned_split = -1;  // set by the autotuner
-  int32_t tuned_waves = 0;
+  ss_tune tune{256, 1, 8, 0, 0, 0};  // launch configuration (slimsell_tune_set / autotune)
   std::mutex mu;
 };
 
@@ -98,6 +101,7 @@ struct LevelArgs {
   const int64_t* cs;
   const int32_t* cl;
   const int32_t* v;
+  const int32_t* deg;  // degree of each row
   const Unit* units;
   const int32_t* pieces;
   int64_t n_units;
@@ -110,9 +114,11 @@ struct LevelArgs {
   int32_t* acc;
   int32_t* arrive;
   uint64_t* any;
-  int32_t* counts;
+  // per-level counters of this root: [(level * kCountSlots + slot) * kCountFields + field]
+  unsigned long long* counters;
   uint64_t* report;
   uint32_t run_id;
+  uint32_t n_pad;    // rows (multiple of 64)
   int32_t level;     // k >= 1
   int32_t slimwork;
   int32_t count_stats;
@@ -120,9 +126,11 @@ struct LevelArgs {
 
 // Kernel launchers (kernels.hip).
 int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
-int launch_level(int semiring, int waves, int64_t max_groups, const LevelArgs& a, void* stream);
+int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
+                 void* stream);
 int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,
                     int32_t* parent, float* real_val, void* stream);
 int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream);
+int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count, void* stream);
 
 }  // namespace ss

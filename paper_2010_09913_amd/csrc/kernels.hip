@@ -30,54 +30,91 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 }
 
 // ------------------------------------------------------------ semirings ---
+//
+// Gathers use raw buffer loads: an offset past the end of the buffer returns
+// zero without a memory access, so a padding cell (-1) or a bitmap miss needs
+// no branch and every load of an unrolled block is issued before the first
+// wait.
+//
+// Each policy gives: live(row), true while the row's value can still change
+// (the SlimWork criterion of Section III-C); block<U>(c, acc), the product
+// terms of U columns for this lane's row (the gathers); the order-independent
+// atomic used to merge SlimChunk pieces; post(row, acc), the per-semiring
+// post-processing of the listing in Section III-A; and publish(chunk, mask),
+// which stores the chunk's new frontier word where the frontier is a bitmap.
 
-// Tropical (min, +), Section III-A: x_k = f_k = A' (x) f_{k-1}, A' has 1 on
-// edges, 0 on the diagonal and infinity elsewhere.  The frontier is the
-// distance vector itself.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kOob = 0x80000000u;  // any offset >= the buffer size reads as 0
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ uint32_t off_of(int32_t c, int shift) {
+  return c >= 0 ? ((uint32_t)c << shift) : kOob;
+}
+
+// Returning atomics, so that the wait that follows covers their completion.
+__device__ __forceinline__ void keep(int32_t v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Tropical (min, +): x_k = f_k = A' (x) f_{k-1}, A' has 1 on edges, 0 on the
+// diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
   using Acc = int32_t;
-  using Val = int32_t;
-  static constexpr int kId = SS_TROPICAL;
   __device__ static Acc identity() { return kInf; }
-  __device__ static Val load(const LevelArgs& a, int32_t c) { return a.state[c]; }
-  // 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
-  __device__ static Acc term(const LevelArgs& a, Val y) { return (y < a.level) ? y + 1 : kInf; }
-  __device__ static Acc combine(Acc x, Acc y) { return x < y ? x : y; }
+  __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
-  __device__ static void atomic_combine(int32_t* p, Acc v) {
-    if (v != kInf) atomicMin(p, v);
+  // terms 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
+  template <int U>
+  __device__ static Acc block(const LevelArgs& a, Rsrc r, const int32_t (&c)[U], Acc acc) {
+    int32_t y[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] = __builtin_amdgcn_raw_buffer_load_b32(r, off_of(c[t], 2), 0, 0);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int32_t term = (c[t] >= 0 && y[t] < a.level) ? y[t] + 1 : kInf;
+      acc = term < acc ? term : acc;
+    }
+    return acc;
   }
+  __device__ static void atomic_combine(int32_t* p, Acc v) { keep(atomicMin(p, v)); }
   __device__ static Acc take(int32_t* p) { return atomicExch(p, kInf); }
-  // f_k^row = min(f_{k-1}^row, acc): the diagonal of A' keeps the old value
+  // f_k^row = min(f_{k-1}^row, acc): the zero diagonal of A' keeps the old value
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    int32_t own = a.state[row];
-    bool fresh = (own == kInf) && (acc != kInf);
+    const int32_t own = a.state[row];
+    const bool fresh = (own == kInf) && (acc != kInf);
     if (fresh) a.state[row] = acc;
     return fresh;
   }
+  __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
 };
 
-// Real (+, *), Section III-A: x_k = A (x) f_{k-1}; f_k = [x_k (.) g_k != 0];
-// d^row = k where the row enters the frontier.  Sums of 0/1 values of at most
-// the vertex degree are exact in fp32.
+// Real (+, *): x_k = A (x) f_{k-1}; f_k = [x_k (.) g_k != 0]; d^row = k where
+// the row enters the frontier.  Sums of 0/1 values of at most the degree are
+// exact in fp32.
 struct Real {
   using Acc = float;
-  using Val = float;
-  static constexpr int kId = SS_REAL;
   __device__ static Acc identity() { return 0.0f; }
-  __device__ static Val load(const LevelArgs& a, int32_t c) {
-    return static_cast<const float*>(a.vin)[c];
-  }
-  __device__ static Acc term(const LevelArgs&, Val y) { return y; }
-  __device__ static Acc combine(Acc x, Acc y) { return x + y; }
+  __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  template <int U>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+    float y[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t)
+      y[t] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off_of(c[t], 2), 0, 0));
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc += y[t];
+    return acc;
+  }
   __device__ static void atomic_combine(int32_t* p, Acc v) {
-    if (v != 0.0f) atomicAdd(reinterpret_cast<float*>(p), v);
+    keep(__float_as_int(atomicAdd(reinterpret_cast<float*>(p), v)));
   }
   __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<float*>(p), 0.0f); }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    uint8_t gg = a.g[row];
-    bool fresh = (acc * (float)gg) != 0.0f;
+    const uint8_t gg = a.g[row];
+    const bool fresh = (acc * (float)gg) != 0.0f;
     static_cast<float*>(a.vout)[row] = fresh ? 1.0f : 0.0f;
     if (fresh) {
       a.d[row] = a.level;
@@ -86,26 +123,30 @@ struct Real {
     }
     return fresh;
   }
+  __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
 };
 
-// Boolean (|, &), Section III-A: x_k = A (x) f_{k-1}; f_k = x_k & g_k.
+// Boolean (|, &): x_k = A (x) f_{k-1}; f_k = x_k & g_k with a uint8 frontier.
 struct Boolean {
   using Acc = uint32_t;
-  using Val = uint8_t;
-  static constexpr int kId = SS_BOOLEAN;
   __device__ static Acc identity() { return 0u; }
-  __device__ static Val load(const LevelArgs& a, int32_t c) {
-    return static_cast<const uint8_t*>(a.vin)[c];
-  }
-  __device__ static Acc term(const LevelArgs&, Val y) { return (Acc)y; }
-  __device__ static Acc combine(Acc x, Acc y) { return x | y; }
+  __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  template <int U>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+    uint32_t y[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] = __builtin_amdgcn_raw_buffer_load_b8(r, off_of(c[t], 0), 0, 0);
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc |= y[t];
+    return acc;
+  }
   __device__ static void atomic_combine(int32_t* p, Acc v) {
-    if (v) atomicOr(reinterpret_cast<uint32_t*>(p), v);
+    keep((int32_t)atomicOr(reinterpret_cast<uint32_t*>(p), v));
   }
   __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<uint32_t*>(p), 0u); }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    bool fresh = (acc != 0u) && (a.g[row] != 0);
+    const bool fresh = (acc != 0u) && (a.g[row] != 0);
     static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
     if (fresh) {
       a.d[row] = a.level;
@@ -113,79 +154,107 @@ struct Boolean {
     }
     return fresh;
   }
+  __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
 };
 
-// Sel-max (max, *), Section III-A: x_k = A (x) x_{k-1};
-// p_k = p_{k-1} + NOT(p_{k-1}) (.) x_k; f_k = NOT NOT x_k minus the visited
-// set; then x_k <- NOT NOT x_k (.) v with v = original ID + 1, so the max
-// picks the largest original ID among the neighbours one level closer.
+// Sel-max (max, *): x_k = A (x) x_{k-1}; p_k = p_{k-1} + NOT(p_{k-1}) (.) x_k;
+// f_k = NOT NOT x_k minus the visited set; x_k <- NOT NOT x_k (.) v with
+// v = original ID + 1, so the max picks the largest original ID among the
+// neighbours one level closer.  The x vector is held factored as
+// x_{k-1} = f_{k-1} (.) v: a frontier bitmap with one 64-bit word per chunk
+// (the wavefront ballot of the rows that entered the frontier) and the static
+// v.  A gather tests one bit and reads v only on a hit, so the product is
+// evaluated exactly while the gathered array is 32 times smaller.
 struct SelMax {
   using Acc = int32_t;
-  using Val = int32_t;
-  static constexpr int kId = SS_SELMAX;
   __device__ static Acc identity() { return 0; }
-  __device__ static Val load(const LevelArgs& a, int32_t c) {
-    return static_cast<const int32_t*>(a.vin)[c];
+  __device__ static Rsrc rsrc(const LevelArgs& a) {
+    return make_rsrc(a.vin, (uint32_t)(a.n_pad / kC) * 8u);
   }
-  __device__ static Acc term(const LevelArgs&, Val y) { return y; }
-  __device__ static Acc combine(Acc x, Acc y) { return x > y ? x : y; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
-  __device__ static void atomic_combine(int32_t* p, Acc v) {
-    if (v != 0) atomicMax(p, v);
+  template <int U>
+  __device__ static Acc block(const LevelArgs& a, Rsrc r, const int32_t (&c)[U], Acc acc) {
+    const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
+    uint32_t w[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t)  // the 32-bit half of the chunk word holding bit c
+      w[t] = __builtin_amdgcn_raw_buffer_load_b32(r, c[t] >= 0 ? ((uint32_t)c[t] >> 5) << 2 : kOob,
+                                                  0, 0);
+    int32_t x[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const bool hit = c[t] >= 0 && ((w[t] >> (c[t] & 31)) & 1u);
+      x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
+    return acc;
   }
+  __device__ static void atomic_combine(int32_t* p, Acc v) { keep(atomicMax(p, v)); }
   __device__ static Acc take(int32_t* p) { return atomicExch(p, 0); }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    int32_t pr = a.state[row];
-    bool fresh = (pr == 0) && (acc != 0);
+    const bool fresh = (a.state[row] == 0) && (acc != 0);
     if (fresh) {
       a.state[row] = acc;
       a.d[row] = a.level;
     }
-    static_cast<int32_t*>(a.vout)[row] = (acc != 0) ? a.v[row] : 0;
     return fresh;
+  }
+  __device__ static void publish(const LevelArgs& a, int32_t chunk, uint64_t mask, int lane) {
+    if (lane == 0) static_cast<uint64_t*>(a.vout)[chunk] = mask;
   }
 };
 
 // ---------------------------------------------------------- level kernel ---
 
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 // Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
-// U independent streaming loads of `col`, then U exec-masked gathers.
+// U independent streaming loads of `col`, then the U gathers of the block.  A
+// lane that is off (its row is final) issues no loads at all.
 template <class S, int U>
-__device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, const int32_t* __restrict__ p,
-                                                 int32_t ncols, typename S::Acc acc) {
+__device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r,
+                                                 const int32_t* __restrict__ p, int32_t ncols,
+                                                 bool on) {
+  typename S::Acc acc = S::identity();
+  if (!on) return acc;
   int32_t j = 0;
   for (; j + U <= ncols; j += U) {
     int32_t c[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
-    typename S::Acc y[U];
-#pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = (c[t] >= 0) ? S::term(a, S::load(a, c[t])) : S::identity();
-#pragma unroll
-    for (int t = 0; t < U; ++t) acc = S::combine(acc, y[t]);
+    acc = S::template block<U>(a, r, c, acc);
     p += (int64_t)U * kC;
   }
   for (; j < ncols; ++j) {
-    int32_t c = __builtin_nontemporal_load(p);
-    if (c >= 0) acc = S::combine(acc, S::term(a, S::load(a, c)));
+    int32_t c[1] = {__builtin_nontemporal_load(p)};
+    acc = S::template block<1>(a, r, c, acc);
     p += kC;
   }
   return acc;
 }
 
+// Post-process the rows of one chunk; returns how many entered the frontier.
 template <class S>
-__device__ __forceinline__ void finish_rows(const LevelArgs& a, int32_t row, typename S::Acc acc,
-                                            int lane) {
-  bool fresh = S::post(a, row, acc);
-  uint64_t found = __ballot(fresh);
-  if (found && lane == 0) {
-    a.any[a.level % kRing] = level_tag(a.run_id, a.level);
-    if (a.count_stats)
-      atomicAdd(&a.counts[(int64_t)a.level * kCountSlots + (blockIdx.x % kCountSlots)],
-                (int32_t)__popcll(found));
-  }
+__device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chunk, int32_t row,
+                                                typename S::Acc acc, int lane) {
+  const bool fresh = S::post(a, row, acc);
+  const uint64_t mask = __ballot(fresh);
+  S::publish(a, chunk, mask, lane);
+  return (uint32_t)__popcll(mask);
 }
 
+// One BFS level.  slimwork: 0 = every row of every chunk is computed;
+// 1 = chunks whose rows are all final are skipped (Section III-C);
+// 2 = additionally a lane whose row is final issues no loads and the sweep
+// stops at the longest row that is still live.
 template <class S, int U>
 __global__ void level_kernel(LevelArgs a) {
   const int lane = threadIdx.x & (kC - 1);
@@ -204,34 +273,69 @@ __global__ void level_kernel(LevelArgs a) {
     if (!prev_found) return;
   }
 
+  const Rsrc rs = S::rsrc(a);
+  // per-wavefront tallies, flushed once at the end
+  uint32_t found = 0, n_chunks = 0;
+  uint64_t n_cols = 0;
+  int32_t max_cl = 0;
+
   for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < a.n_units;
        u += (int64_t)gridDim.x * waves) {
     const Unit w = a.units[u];
     const bool piece = (w.c1 == w.c0 + 1);
     for (int32_t c = w.c0; c < w.c1; ++c) {
       const int32_t row = c * kC + lane;
-      if (a.slimwork && !__any(S::live(a, row))) continue;  // whole chunk final
+      const bool live = S::live(a, row);
+      if (a.slimwork && !__any(live)) continue;  // whole chunk final
       int32_t j0 = 0, j1 = a.cl[c];
       if (piece) { j0 = w.j0; j1 = w.j1; }
+      if (j0 == 0) {
+        ++n_chunks;
+        const int32_t len = a.cl[c];
+        max_cl = len > max_cl ? len : max_cl;
+      }
+      const bool on = (a.slimwork >= 2) ? live : true;
+      int32_t hi = j1;
+      if (a.slimwork >= 2) {
+        const int32_t lim = wave_max(on ? a.deg[row] : 0);
+        hi = lim < j1 ? lim : j1;
+      }
+      const int32_t ncols = hi > j0 ? hi - j0 : 0;
+      n_cols += (uint64_t)ncols;
       const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
-      typename S::Acc acc = sweep<S, U>(a, p, j1 - j0, S::identity());
+      typename S::Acc acc = sweep<S, U>(a, rs, p, ncols, on);
       const int32_t npieces = piece ? a.pieces[c] : 1;
       if (npieces == 1) {
-        finish_rows<S>(a, row, acc, lane);
+        found += finish_rows<S>(a, c, row, acc, lane);
       } else {
-        // SlimChunk: combine this piece, the last one to arrive post-processes
+        // SlimChunk: combine this piece, the last one to arrive post-processes.
+        // Pieces exchange data only through device-scope atomics: each piece's
+        // combine has completed before its arrival is counted, so the last
+        // arrival's exchange sees every piece.
         S::atomic_combine(&a.acc[row], acc);
-        __threadfence();
+        wait_memory();
         int last = 0;
         if (lane == 0) last = (atomicAdd(&a.arrive[c], 1) == npieces - 1);
         last = __shfl(last, 0);
         if (last) {
-          __threadfence();
           acc = S::take(&a.acc[row]);
           if (lane == 0) a.arrive[c] = 0;
-          finish_rows<S>(a, row, acc, lane);
+          found += finish_rows<S>(a, c, row, acc, lane);
         }
       }
+    }
+  }
+  if (lane == 0) {
+    if (found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+    if (a.count_stats && (found | n_chunks | n_cols)) {
+      unsigned long long* ctr =
+          a.counters + ((int64_t)a.level * kCountSlots + (blockIdx.x % kCountSlots)) * kCountFields;
+      if (found) atomicAdd(&ctr[0], (unsigned long long)found);
+      if (n_chunks) {
+        atomicAdd(&ctr[1], (unsigned long long)n_chunks);
+        atomicMax(&ctr[3], (unsigned long long)max_cl);
+      }
+      if (n_cols) atomicAdd(&ctr[2], (unsigned long long)n_cols * kC);
     }
   }
 }
@@ -248,6 +352,7 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_chunks) arrive[r] = 0;
   if (r >= n_pad) return;
+  // sel-max: one bitmap word per chunk is initialised below
   const bool root = (r == root_row);
   const bool phantom = (v[r] == 0);
   if (SEMI == SS_TROPICAL) {
@@ -266,9 +371,9 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
     static_cast<uint8_t*>(va)[r] = root ? 1 : 0;
     static_cast<uint8_t*>(vb)[r] = 0;
     acc[r] = 0;
-  } else {  // SS_SELMAX
-    static_cast<int32_t*>(va)[r] = root ? v[r] : 0;
-    static_cast<int32_t*>(vb)[r] = 0;
+  } else {  // SS_SELMAX: frontier bitmap f_0 = e_r (x_0 = f_0 (.) v), p_0 = x_0
+    if (r < n_chunks)
+      static_cast<uint64_t*>(va)[r] = (r == root_row / kC) ? (1ull << (root_row % kC)) : 0ull;
     state[r] = root ? v[r] : (phantom ? -1 : 0);
     acc[r] = 0;
   }
@@ -337,21 +442,28 @@ int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_
 }
 
 template <class S>
-static void launch_level_t(int waves, unsigned grid, const LevelArgs& a, hipStream_t st) {
-  level_kernel<S, 8><<<grid, waves * kC, 0, st>>>(a);
+static void launch_level_t(int waves, int unroll, unsigned grid, const LevelArgs& a,
+                           hipStream_t st) {
+  if (unroll == 4)
+    level_kernel<S, 4><<<grid, waves * kC, 0, st>>>(a);
+  else if (unroll == 16)
+    level_kernel<S, 16><<<grid, waves * kC, 0, st>>>(a);
+  else
+    level_kernel<S, 8><<<grid, waves * kC, 0, st>>>(a);
 }
 
-int launch_level(int semiring, int waves, int64_t max_groups, const LevelArgs& a, void* stream) {
+int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
+                 void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   int64_t groups = (a.n_units + waves - 1) / waves;
   if (groups < 1) groups = 1;
   if (max_groups > 0 && groups > max_groups) groups = max_groups;
   const unsigned grid = (unsigned)groups;
   switch (semiring) {
-    case SS_TROPICAL: launch_level_t<Tropical>(waves, grid, a, st); break;
-    case SS_REAL: launch_level_t<Real>(waves, grid, a, st); break;
-    case SS_BOOLEAN: launch_level_t<Boolean>(waves, grid, a, st); break;
-    case SS_SELMAX: launch_level_t<SelMax>(waves, grid, a, st); break;
+    case SS_TROPICAL: launch_level_t<Tropical>(waves, unroll, grid, a, st); break;
+    case SS_REAL: launch_level_t<Real>(waves, unroll, grid, a, st); break;
+    case SS_BOOLEAN: launch_level_t<Boolean>(waves, unroll, grid, a, st); break;
+    case SS_SELMAX: launch_level_t<SelMax>(waves, unroll, grid, a, st); break;
     default: return set_error(SS_EINVAL, "unknown semiring");
   }
   return check_launch("level_kernel");
@@ -380,6 +492,16 @@ int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream) {
   unsigned blocks = blocks_for(count, 256);
   if (blocks > 4096) blocks = 4096;
   fill_kernel<int32_t><<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(p, value, count);
+  return check_launch("fill_kernel");
+}
+
+int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count,
+                    void* stream) {
+  if (count <= 0) return SS_OK;
+  unsigned blocks = blocks_for(count, 256);
+  if (blocks > 4096) blocks = 4096;
+  fill_kernel<unsigned long long><<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
+      p, value, count);
   return check_launch("fill_kernel");
 }
 

@@ -62,6 +62,13 @@ def _check(ss, G, g, roots, semi, **kw):
         ex = oracle.expected(g, int(r))
         np.testing.assert_array_equal(dist[i], ex.dist, err_msg=f"{semi} root {r} dist {kw}")
         assert res.iterations[i] == ex.iterations, (semi, r, kw)
+        if res.levels is not None:
+            cap = res.levels["discovered"].shape[1]
+            hist = np.bincount(ex.dist[ex.dist > 0], minlength=ex.iterations + 1)[1:]
+            hist = np.concatenate([hist, np.zeros(max(0, cap - len(hist)), np.int64)])[:cap]
+            np.testing.assert_array_equal(res.levels["discovered"][i], hist)
+            cells = res.levels["active_cells"][i]
+            assert np.all(cells[:ex.iterations] >= 0) and np.all(cells[ex.iterations:] == 0)
         if semi == "selmax":
             np.testing.assert_array_equal(par[i], ex.parent, err_msg=f"root {r} parent {kw}")
         if semi == "real":
@@ -77,9 +84,19 @@ def test_rmat_scale12_tropical_from_the_max_degree_root(ss):
     root = int(np.argmax(g.degree))  # argmax takes the smallest ID among ties
     G = _graph(ss, e, sigma=4096)
     note("c1 root", root)
-    res = _check(ss, G, g, [root], "tropical", level_cap=64)
+    res = _check(ss, G, g, [root], "tropical", level_cap=64, timing=True)
     ref = oracle.semiring_bfs(g, root, oracle.TROPICAL)
     np.testing.assert_array_equal(res.frontier[:ref.iterations], ref.frontier_sizes)
+    # without SlimWork every level streams every non-empty chunk
+    L = ss.layout_build(e.src, e.dst, e.n, sigma=4096)
+    res = G.bfs([root], "tropical", slimwork=0, split_len=0, level_cap=64, timing=True)
+    it = int(res.iterations[0])
+    assert np.all(res.levels["active_cells"][0][:it] == L.cells)
+    assert np.all(res.levels["active_chunks"][0][:it] == (L.cl > 0).sum())
+    assert np.all(res.levels["max_active_cl"][0][:it] == L.max_cl)
+    assert np.all(res.levels["ms"][0][:it] > 0)
+    assert res.runs["launches"][0] >= it + 1
+    assert res.runs["bfs_ms"][0] >= res.runs["kernel_ms"][0] > 0
 
 
 # ---------------------------------------------------- small-matrix sweeps
@@ -93,12 +110,13 @@ def test_all_semirings_slimwork_and_splits(ss, kind, sigma):
     roots = graphgen.pick_roots(e, 3, seed=9)
     for semi in SEMIS:
         ref = oracle.semiring_bfs(g, int(roots[-1]), OR_SEMI[semi])
-        for slimwork in (False, True):
+        for slimwork in (0, 1, 2):
             for split in (0, 16, 64, 256):
                 note(kind, sigma, semi, slimwork, split)
                 res = _check(ss, G, g, roots, semi, slimwork=slimwork, split_len=split,
                              level_cap=64)
-                np.testing.assert_array_equal(res.frontier[:ref.iterations], ref.frontier_sizes)
+                np.testing.assert_array_equal(res.levels["discovered"][-1][:ref.iterations],
+                                              ref.frontier_sizes)
 
 
 @pytest.mark.parametrize("waves", [1, 2, 4, 8, 16])
@@ -217,12 +235,16 @@ def test_rmat_scale20_all_semirings(ss):
     roots = graphgen.pick_roots(e, 16, seed=1001)
     for semi in SEMIS:
         note("s20", semi)
-        _check(ss, G, g, roots, semi, slimwork=True)
-    note("s20 selmax no slimwork")
-    _check(ss, G, g, roots[:4], "selmax", slimwork=False)
+        _check(ss, G, g, roots, semi, slimwork=2)
+    for mode in (0, 1):
+        note("s20 selmax slimwork", mode)
+        _check(ss, G, g, roots[:4], "selmax", slimwork=mode)
     ref = oracle.semiring_bfs(g, int(roots[0]), oracle.BOOLEAN)
     res = G.bfs(roots[:1], "boolean", level_cap=64)
     np.testing.assert_array_equal(res.frontier[:ref.iterations], ref.frontier_sizes)
+    # m_cc from the library's degrees equals the oracle's
+    deg = G.degrees()
+    np.testing.assert_array_equal(deg, g.degree)
 
 
 @pytest.mark.parametrize("kind", ["rmat", "er"])
@@ -238,5 +260,25 @@ def test_scale22_selmax_split_sweep(ss, kind):
     roots = graphgen.pick_roots(e, 64, seed=seed)[:3]
     for split in (256, 1024, 4096):
         note("s22", kind, split)
-        _check(ss, G, g, roots, "selmax", slimwork=True, split_len=split)
+        _check(ss, G, g, roots, "selmax", slimwork=2, split_len=split)
+    _check(ss, G, g, roots[:1], "selmax", slimwork=1, split_len=1024)
     _CACHE.clear()
+
+
+@pytest.mark.parametrize("tune", [
+    dict(unroll=4), dict(unroll=16), dict(max_groups=64), dict(max_groups=7, waves_per_group=2),
+    dict(pack_cols=0), dict(pack_cols=40, split_len=96), dict(split_len=0, pack_cols=0),
+])
+def test_launch_configurations_give_identical_results(ss, tune):
+    e = graphgen.rmat(13, 16, seed=11)
+    g = _csr(e)
+    G = ss.Graph.from_edgelist(e, sigma=0)
+    G.set_tune(**tune)
+    roots = graphgen.pick_roots(e, 3, seed=12)
+    for semi in SEMIS:
+        for mode in (1, 2):
+            note("tune", tune, semi, mode)
+            _check(ss, G, g, roots, semi, slimwork=mode)
+    with pytest.raises(ss.SlimSellError):
+        G.set_tune(unroll=3)
+    G.close()
