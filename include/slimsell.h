@@ -116,6 +116,30 @@ typedef struct ss_graph ss_graph;
 int slimsell_build(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t C,
                    int32_t sigma, void* stream, ss_graph** out);
 
+/*
+ * Several graphs as one device graph: the disjoint union of their SlimSell
+ * layouts, each graph's rows padded to whole chunks, so no chunk mixes graphs.
+ * Vertex v of graph i has the union ID voff_i + v with voff_i = n_0 + ... +
+ * n_{i-1}.  Single-root BFS (slimsell_bfs) treats the union as one graph;
+ * slimsell_bfs_batch runs up to 64 roots in every graph at once.
+ *   num_graphs     : >= 1.
+ *   edge_offsets   : host int64[num_graphs + 1]; graph i's tuples are
+ *                    src/dst[edge_offsets[i] .. edge_offsets[i+1]).
+ *   src, dst       : host int32, graph-local IDs in [0, n_i).
+ *   n_per_graph    : host int32[num_graphs], each >= 1.
+ *   C, sigma       : as slimsell_layout_build, applied to every graph
+ *                    (sigma 0 = sort all rows of that graph).
+ * Errors: as slimsell_build; the union must have fewer than 2^31 rows.
+ */
+int slimsell_build_multi(int32_t num_graphs, const int64_t* edge_offsets, const int32_t* src,
+                         const int32_t* dst, const int32_t* n_per_graph, int32_t C,
+                         int32_t sigma, void* stream, ss_graph** out);
+
+/* Number of graphs in a (possibly multi-graph) device graph and, if not NULL,
+ * each graph's vertex count and union-ID offset (host int64[num_graphs]). */
+int slimsell_graph_parts(const ss_graph* g, int32_t* num_graphs, int64_t* n_per_graph,
+                         int64_t* vertex_offset);
+
 /* Upload an existing host layout to the current device. */
 int slimsell_build_from_layout(const ss_layout* layout, void* stream, ss_graph** out);
 
@@ -155,6 +179,44 @@ typedef struct {
 /* Set / read the graph's launch configuration.  SS_EINVAL on a bad field. */
 int slimsell_tune_set(ss_graph* g, const ss_tune* tune);
 int slimsell_tune_get(const ss_graph* g, ss_tune* tune);
+
+/*
+ * Autotuner: measures the level kernel's launch configuration on this graph
+ * and stores the fastest in it (slimsell_tune_set).  Coordinate descent over
+ * split_len {0, 64, ..., 4096}, waves_per_group {1, ..., 16}, unroll
+ * {4, 8, 16}, max_groups {0, 1024, 4096} and pack_cols {0, 32, 128}, two
+ * passes; each configuration is timed (events, init to finalise) over the
+ * given roots, median of `repeats`.  Results are cached per graph class
+ * (semiring, batched, log2 n, mean degree, degree skew) for the process.
+ * Results of BFS calls do not depend on the configuration.
+ *   semiring   : the semiring to tune for (ignored when batched = 1).
+ *   batched    : 1 = tune for slimsell_bfs_batch (64-root boolean SpMM).
+ *   roots      : host int32[num_roots], roots to time (num_roots >= 1).
+ *   repeats    : timed repetitions per configuration (0 = 3).
+ *   force      : 1 = ignore the class cache.
+ * On return *result holds the chosen configuration and its time, the time of
+ * the configuration in force before the call, and the evaluation count.
+ */
+typedef struct {
+  uint32_t size;
+  int32_t semiring;
+  int32_t batched;
+  int32_t num_roots;
+  const int32_t* roots;
+  int32_t repeats;
+  int32_t force;
+  void* stream;
+} ss_autotune_opts;
+
+typedef struct {
+  ss_tune best;
+  float best_ms;        /* summed BFS time over the roots, chosen configuration */
+  float before_ms;      /* same, configuration in force before the call */
+  int32_t evaluated;    /* configurations timed (0 when served from the cache) */
+  int32_t from_cache;
+} ss_autotune_result;
+
+int slimsell_autotune(ss_graph* g, const ss_autotune_opts* opts, ss_autotune_result* result);
 
 /* Release a graph and its device memory. */
 void slimsell_free(ss_graph* g);
@@ -244,6 +306,29 @@ typedef struct {
  */
 int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiring s,
                  const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
+
+/*
+ * Batched BFS as a boolean SpMM (not in the paper; multi-source BFS): every
+ * row carries a 64-bit frontier mask, one bit per root, so one sweep of the
+ * SlimSell layout advances up to 64 BFS at once: X = OR over the row's
+ * neighbours of F, new = X & ~visited.  In a multi-graph, slot b runs root b
+ * of every graph in the same sweep (the graphs are disjoint), so all graphs
+ * are solved by one level loop.
+ *   roots           : host int32[num_graphs * roots_per_graph]; entry
+ *                     [i * roots_per_graph + b] is a graph-local root of graph
+ *                     i, or -1 for an unused slot.
+ *   roots_per_graph : 1..64.
+ *   dist            : device int32; graph i's block starts at
+ *                     roots_per_graph * voff_i and is laid out
+ *                     [roots_per_graph][n_i] (hop distances, -1 unreachable
+ *                     or unused slot).  For one graph this is [b][n].
+ * opts as slimsell_bfs (slimwork, split via the graph's configuration,
+ * statistics; iterations_out[0] receives the level count of the union).
+ * Levels are capped at 65534.  Errors: SS_EINVAL (root out of range,
+ * roots_per_graph out of range), SS_EITER, SS_EHIP, SS_ENOMEM.
+ */
+int slimsell_bfs_batch(ss_graph* g, const int32_t* roots, int32_t roots_per_graph,
+                       const ss_bfs_opts* opts, int32_t* dist);
 
 /* Wait for all work on `stream`; returns SS_EHIP if any of it failed. */
 int slimsell_sync(void* stream);

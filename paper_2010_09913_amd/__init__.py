@@ -134,6 +134,37 @@ class Graph:
     def from_edgelist(cls, g, sigma: int = 0, stream=None) -> "Graph":
         return cls(g.src, g.dst, g.n, sigma=sigma, stream=stream)
 
+    @classmethod
+    def from_many(cls, graphs, sigma: int = 0, stream=None) -> "Graph":
+        """Disjoint union of several edge lists as one device graph
+        (slimsell_build_multi); graph i's vertex v is union vertex voff_i + v."""
+        lib = _native.load()
+        offs = np.zeros(len(graphs) + 1, np.int64)
+        offs[1:] = np.cumsum([g.m for g in graphs])
+        src = _i32(np.concatenate([g.src for g in graphs])) if graphs else np.zeros(0, np.int32)
+        dst = _i32(np.concatenate([g.dst for g in graphs])) if graphs else np.zeros(0, np.int32)
+        ns = _i32([g.n for g in graphs])
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        self.n = int(ns.sum())
+        self.sigma = sigma
+        st = ctypes.c_void_p() if stream is None else _stream_handle(stream)
+        check(lib.slimsell_build_multi(len(graphs), offs.ctypes.data_as(_native.c_i64p),
+                                       _p32(src), _p32(dst), _p32(ns), CHUNK, sigma, st,
+                                       ctypes.byref(self._h)))
+        return self
+
+    def parts(self) -> tuple[np.ndarray, np.ndarray]:
+        """(vertices per graph, union-ID offset per graph)."""
+        lib = _native.load()
+        k = ctypes.c_int32()
+        check(lib.slimsell_graph_parts(self._h, ctypes.byref(k), None, None))
+        ns = np.zeros(k.value, np.int64)
+        off = np.zeros(k.value, np.int64)
+        check(lib.slimsell_graph_parts(self._h, ctypes.byref(k), ns.ctypes.data_as(_native.c_i64p),
+                                       off.ctypes.data_as(_native.c_i64p)))
+        return ns, off
+
     def info(self) -> dict:
         vals = [ctypes.c_int64() for _ in range(5)]
         check(_native.load().slimsell_graph_info(self._h, *[ctypes.byref(x) for x in vals]))
@@ -226,6 +257,68 @@ class Graph:
         if runs is not None:
             run_d = {f: np.array([getattr(runs[i], f) for i in range(nr)]) for f in RUN_FIELDS}
         return BfsResult(dist, parent, real_val, iters[:nr].copy(), levels, run_d)
+
+    def bfs_batch(self, roots, *, slimwork: int = 2, max_levels: int = 0, stream=None,
+                  level_cap: int = 0, timing: bool = False, counters: bool = None, dist=None):
+        """Batched BFS (64-bit frontier masks).  roots: int array [num_graphs, rpg]
+        (graph-local IDs, -1 = unused slot) or [rpg] for a single graph.  Returns
+        (dist tensor, iterations, levels, runs); dist holds each graph's block
+        [rpg][n_i] at offset rpg * voff_i."""
+        import torch
+        roots = _i32(np.atleast_2d(roots))
+        ng, rpg = roots.shape
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if dist is None:
+            dist = torch.empty(rpg * self.n, dtype=torch.int32, device=dev)
+        elif dist.dtype != torch.int32 or not dist.is_cuda or dist.numel() != rpg * self.n:
+            raise ValueError("dist must be an int32 device tensor of rpg * n elements")
+        iters = np.zeros(1, np.int32)
+        o = BfsOpts()
+        o.size = ctypes.sizeof(BfsOpts)
+        o.slimwork = int(slimwork)
+        o.split_len = -1
+        o.max_levels = max_levels
+        o.stream = _stream_handle(stream)
+        o.iterations_out = iters.ctypes.data_as(_native.c_i32p)
+        if counters is None:
+            counters = level_cap > 0
+        o.flags = (_native.SS_STATS_TIME if timing else 0) | (
+            _native.SS_STATS_COUNTERS if counters else 0)
+        lvl = runs = None
+        if level_cap > 0:
+            lvl = (_native.LevelStats * level_cap)()
+            o.level_cap = level_cap
+            o.level_stats_out = lvl
+        if timing or level_cap > 0:
+            runs = (_native.RunStats * 1)()
+            o.run_stats_out = runs
+        check(_native.load().slimsell_bfs_batch(self._h, _p32(roots.reshape(-1)), rpg,
+                                                ctypes.byref(o), ctypes.c_void_p(dist.data_ptr())))
+        levels = run_d = None
+        if lvl is not None:
+            levels = {f: np.array([getattr(x, f) for x in lvl]) for f in LEVEL_FIELDS}
+        if runs is not None:
+            run_d = {f: getattr(runs[0], f) for f in RUN_FIELDS}
+        return dist, int(iters[0]), levels, run_d
+
+    def autotune(self, roots, semiring="selmax", *, batched: bool = False, repeats: int = 3,
+                 force: bool = False, stream=None) -> dict:
+        """Time launch configurations on these roots and keep the fastest."""
+        roots2 = _i32(np.atleast_2d(roots)) if batched else _i32(np.atleast_1d(roots))[None, :]
+        roots = roots2.reshape(-1)
+        o = _native.AutotuneOpts()
+        o.size = ctypes.sizeof(_native.AutotuneOpts)
+        o.semiring = _semiring(semiring)
+        o.batched = 1 if batched else 0
+        o.num_roots = int(roots2.shape[1])
+        o.roots = _p32(roots)
+        o.repeats = repeats
+        o.force = 1 if force else 0
+        o.stream = _stream_handle(stream)
+        r = _native.AutotuneResult()
+        check(_native.load().slimsell_autotune(self._h, ctypes.byref(o), ctypes.byref(r)))
+        return dict(best={f: getattr(r.best, f) for f in self.TUNE_FIELDS}, best_ms=r.best_ms,
+                    before_ms=r.before_ms, evaluated=r.evaluated, from_cache=bool(r.from_cache))
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

@@ -25,6 +25,7 @@ EXPORTS = [
     "slimsell_build", "slimsell_build_from_layout", "slimsell_graph_info",
     "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get", "slimsell_free",
     "slimsell_bfs", "slimsell_sync", "slimsell_last_error", "slimsell_version",
+    "slimsell_build_multi", "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
 ]
 
 
@@ -58,6 +59,21 @@ class Tune(ctypes.Structure):
         ("split_len", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
         ("unroll", ctypes.c_int32), ("max_groups", ctypes.c_int32),
         ("pack_cols", ctypes.c_int32), ("pad0", ctypes.c_int32),
+    ]
+
+
+class AutotuneOpts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32), ("semiring", ctypes.c_int32), ("batched", ctypes.c_int32),
+        ("num_roots", ctypes.c_int32), ("roots", c_i32p), ("repeats", ctypes.c_int32),
+        ("force", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+class AutotuneResult(ctypes.Structure):
+    _fields_ = [
+        ("best", Tune), ("best_ms", ctypes.c_float), ("before_ms", ctypes.c_float),
+        ("evaluated", ctypes.c_int32), ("from_cache", ctypes.c_int32),
     ]
 
 
@@ -108,6 +124,12 @@ def load() -> ctypes.CDLL:
     lib.slimsell_bfs.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(BfsOpts), vp, vp, vp]
     lib.slimsell_sync.argtypes = [vp]
+    lib.slimsell_build_multi.argtypes = [ctypes.c_int32, c_i64p, c_i32p, c_i32p, c_i32p,
+                                         ctypes.c_int32, ctypes.c_int32, vp, vpp]
+    lib.slimsell_graph_parts.argtypes = [vp, c_i32p, c_i64p, c_i64p]
+    lib.slimsell_bfs_batch.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.POINTER(BfsOpts), vp]
+    lib.slimsell_autotune.argtypes = [vp, ctypes.POINTER(AutotuneOpts),
+                                      ctypes.POINTER(AutotuneResult)]
     lib.slimsell_last_error.argtypes = []
     lib.slimsell_last_error.restype = ctypes.c_char_p
     lib.slimsell_version.argtypes = []
@@ -115,8 +137,8 @@ def load() -> ctypes.CDLL:
     for name in ("slimsell_layout_build", "slimsell_layout_view", "slimsell_build",
                  "slimsell_build_from_layout", "slimsell_graph_info",
                  "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get",
-                 "slimsell_bfs",
-                 "slimsell_sync"):
+                 "slimsell_bfs", "slimsell_sync", "slimsell_build_multi",
+                 "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -25,6 +25,7 @@ SOURCES = [
     ("layout.cpp", HOST_FLAGS),
     ("kernels.hip", DEVICE_FLAGS),
     ("api.hip", DEVICE_FLAGS),
+    ("autotune.hip", DEVICE_FLAGS),
 ]
 
 

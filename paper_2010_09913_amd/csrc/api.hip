@@ -63,7 +63,9 @@ static void release_graph(Graph* g) {
   (void)hipSetDevice(g->device);
   void* ptrs[] = {g->d_col,     g->d_cs,   g->d_cl,    g->d_v,     g->d_perm, g->d_deg,
                   g->ws.vec_a,  g->ws.vec_b, g->ws.state, g->ws.g, g->ws.d,
-                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters};
+                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters,
+                  g->d_voff,    g->bw.vis, g->bw.fa,   g->bw.fb,   g->bw.acc64,
+                  g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* ev : g->ev_pool)
@@ -176,6 +178,7 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.rv, g.n_pad))) return rc;
   if ((rc = dalloc(&ws.acc, g.n_pad))) return rc;
   if ((rc = dalloc(&ws.arrive, g.n_chunks))) return rc;
+  SS_HIP(hipMemset(ws.arrive, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.n_chunks)));
   if ((rc = dalloc(&ws.any, kRing))) return rc;
   SS_HIP(hipMemset(ws.any, 0, sizeof(uint64_t) * kRing));
   void* h = nullptr;
@@ -217,12 +220,247 @@ static int wait_report(Graph& g, int32_t level, uint32_t run_id, hipStream_t st,
   }
 }
 
+
+ss_bfs_opts default_opts() {
+  ss_bfs_opts d;
+  std::memset(&d, 0, sizeof(d));
+  d.size = sizeof(d);
+  d.slimwork = 2;
+  d.split_len = -1;
+  return d;
+}
+
+uint32_t next_run_id(Graph& g) {
+  g.run_id = (g.run_id >= 0x7FFFFFF0u) ? 1u : g.run_id + 1;
+  return g.run_id;
+}
+
+// Validated launch parameters of one call (shared by single-root and batched BFS).
+struct RunPlan {
+  int waves = 4, unroll = 8;
+  int64_t max_groups = 0, cap = 0, lcap = 0, words_per_run = 0;
+  bool timing = false, counting = false;
+  int32_t slimwork = 2;
+  UnitList* ul = nullptr;
+};
+
+// Per-call record of what was launched, for the statistics epilogue.
+struct RunLog {
+  explicit RunLog(size_t runs) : ev_first(runs, 0), launches(runs, 0), iters(runs, 0) {}
+  size_t next_ev = 0;
+  std::vector<size_t> ev_first;
+  std::vector<int32_t> launches;
+  std::vector<int32_t> iters;
+};
+
+static int plan_run(Graph& g, const ss_bfs_opts* o, int32_t runs, int64_t default_cap,
+                    hipStream_t st, RunPlan* p) {
+  if (o->size != sizeof(ss_bfs_opts)) return set_error(SS_EINVAL, "opts->size mismatch");
+  if (o->slimwork < 0 || o->slimwork > 2) return set_error(SS_EINVAL, "slimwork must be 0, 1 or 2");
+  p->waves = o->waves_per_group ? o->waves_per_group : g.tune.waves_per_group;
+  if (p->waves != 1 && p->waves != 2 && p->waves != 4 && p->waves != 8 && p->waves != 16)
+    return set_error(SS_EINVAL, "waves_per_group must be 1, 2, 4, 8 or 16");
+  int32_t split = o->split_len;
+  if (split < -1) return set_error(SS_EINVAL, "split_len must be >= -1");
+  if (split == -1) split = g.tune.split_len;
+  const int32_t pack = g.tune.pack_cols < 0 ? (split > 0 ? split : 0) : g.tune.pack_cols;
+  p->unroll = g.tune.unroll;
+  p->max_groups = g.tune.max_groups;
+  p->cap = (o->max_levels > 0) ? std::min<int64_t>(o->max_levels, default_cap) : default_cap;
+  if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
+  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS)) return set_error(SS_EINVAL, "bad flags");
+  p->slimwork = o->slimwork;
+  int rc = get_units(g, split, pack, &p->ul);
+  if (rc) return rc;
+  p->timing = (o->flags & SS_STATS_TIME) != 0;
+  p->lcap = o->level_cap;
+  p->counting = (o->flags & SS_STATS_COUNTERS) && p->lcap > 0 && o->level_stats_out;
+  p->words_per_run = (p->lcap + 1) * kCountSlots * kCountFields;
+  if (p->counting) {
+    rc = ensure_counters(g, p->words_per_run * runs);
+    if (rc) return rc;
+    rc = launch_fill_u64(g.ws.counters, 0ull, p->words_per_run * runs, st);
+    if (rc) return rc;
+  }
+  return SS_OK;
+}
+
+static int mark_event(Graph& g, const RunPlan& p, size_t& next_ev, hipStream_t st,
+                      size_t* first) {
+  if (!p.timing) return SS_OK;
+  if (first) *first = next_ev;
+  hipEvent_t ev;
+  int rc = pool_event(g, next_ev++, &ev);
+  if (rc) return rc;
+  SS_HIP(hipEventRecord(ev, st));
+  return SS_OK;
+}
+
+static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uint32_t run,
+                           int32_t run_idx) {
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.col = g.d_col;
+  a.cs = g.d_cs;
+  a.cl = g.d_cl;
+  a.v = g.d_v;
+  a.deg = g.d_deg;
+  a.units = p.ul->d_units;
+  a.pieces = p.ul->d_pieces;
+  a.n_units = p.ul->count;
+  a.state = g.ws.state;
+  a.g = g.ws.g;
+  a.d = g.ws.d;
+  a.rv = g.ws.rv;
+  a.acc = g.ws.acc;
+  a.arrive = g.ws.arrive;
+  a.any = g.ws.any;
+  a.counters = p.counting ? g.ws.counters + p.words_per_run * run_idx : nullptr;
+  a.report = g.ws.d_report;
+  a.run_id = run;
+  a.n_pad = (uint32_t)g.n_pad;
+  a.slimwork = p.slimwork;
+  (void)o;
+  return a;
+}
+
+// The level loop of one BFS run: level kernels are enqueued kLookahead ahead
+// of the level being waited on; the run ends at the first level that
+// discovers nothing.
+static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void* buf_a,
+                      void* buf_b, hipStream_t st, RunLog* log, int32_t run_idx) {
+  constexpr int kLookahead = 2;
+  int32_t launched = 0;
+  auto launch = [&](int32_t k) -> int {
+    a.level = k;
+    a.vin = (k & 1) ? buf_a : buf_b;
+    a.vout = (k & 1) ? buf_b : buf_a;
+    a.count_stats = (p.counting && k <= p.lcap) ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p.timing) {
+      int pr;
+      if ((pr = pool_event(g, log->next_ev++, &e0))) return pr;
+      if ((pr = pool_event(g, log->next_ev++, &e1))) return pr;
+      SS_HIP(hipEventRecord(e0, st));
+    }
+    int lr = launch_level(policy, p.waves, p.unroll, p.max_groups, a, st);
+    if (lr) return lr;
+    if (p.timing) SS_HIP(hipEventRecord(e1, st));
+    return SS_OK;
+  };
+  for (int32_t j = 1;; ++j) {
+    while (launched < j + kLookahead && launched <= p.cap) {
+      int rc = launch(++launched);
+      if (rc) return rc;
+    }
+    bool found = false;
+    int rc = wait_report(g, j, a.run_id, st, &found);
+    if (rc) return rc;
+    if (!found) {
+      log->iters[run_idx] = j;
+      break;
+    }
+    if (j >= p.cap) {
+      (void)hipStreamSynchronize(st);
+      return set_error(SS_EITER, "level cap reached before the BFS finished");
+    }
+  }
+  log->launches[run_idx] = launched;
+  return SS_OK;
+}
+
+// Statistics epilogue: wait for the stream, then fill run and level records.
+static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32_t runs,
+                         const RunLog& log, hipStream_t st) {
+  const bool want_levels = o->level_stats_out && p.lcap > 0;
+  if (!(p.timing || p.counting || o->run_stats_out || want_levels)) return SS_OK;
+  SS_HIP(hipStreamSynchronize(st));
+  std::vector<unsigned long long> h;
+  if (p.counting) {
+    h.resize((size_t)(p.words_per_run * runs));
+    SS_HIP(hipMemcpy(h.data(), g.ws.counters, sizeof(unsigned long long) * h.size(),
+                     hipMemcpyDeviceToHost));
+  }
+  auto ev = [&](size_t i) { return static_cast<hipEvent_t>(g.ev_pool[i]); };
+  for (int32_t r = 0; r < runs; ++r) {
+    float kernel_ms = 0.f, bfs_ms = 0.f;
+    std::vector<float> lvl_ms((size_t)log.launches[r], 0.f);
+    if (p.timing) {
+      const size_t e = log.ev_first[r];
+      for (int32_t k = 0; k < log.launches[r]; ++k) {
+        float ms = 0.f;
+        SS_HIP(hipEventElapsedTime(&ms, ev(e + 1 + 2 * k), ev(e + 2 + 2 * k)));
+        lvl_ms[k] = ms;
+        kernel_ms += ms;
+      }
+      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1 + 2 * log.launches[r])));
+    }
+    if (o->run_stats_out) {
+      ss_run_stats& rs = o->run_stats_out[r];
+      rs.iterations = log.iters[r];
+      rs.launches = log.launches[r];
+      rs.kernel_ms = kernel_ms;
+      rs.bfs_ms = bfs_ms;
+    }
+    if (want_levels) {
+      for (int64_t k = 1; k <= p.lcap; ++k) {
+        ss_level_stats& ls = o->level_stats_out[r * p.lcap + (k - 1)];
+        std::memset(&ls, 0, sizeof(ls));
+        if (k > log.iters[r]) continue;
+        ls.ms = p.timing ? lvl_ms[k - 1] : 0.f;
+        if (p.counting) {
+          const unsigned long long* base = h.data() + p.words_per_run * r;
+          for (int q = 0; q < kCountSlots; ++q) {
+            const unsigned long long* f = base + (k * kCountSlots + q) * kCountFields;
+            ls.discovered += (int64_t)f[0];
+            ls.active_chunks += (int64_t)f[1];
+            ls.active_cells += (int64_t)f[2];
+            ls.max_active_cl = std::max<int64_t>(ls.max_active_cl, (int64_t)f[3]);
+          }
+        }
+      }
+    }
+  }
+  return SS_OK;
+}
+
+static int ensure_batch_workspace(Graph& g, int64_t roots,
+                                  const std::vector<unsigned long long>& full_per_graph,
+                                  hipStream_t st) {
+  BatchWorkspace& b = g.bw;
+  int rc;
+  if (!b.vis) {
+    b.n_pad = g.n_pad;
+    if ((rc = dalloc(&b.vis, g.n_pad))) return rc;
+    if ((rc = dalloc(&b.fa, g.n_pad))) return rc;
+    if ((rc = dalloc(&b.fb, g.n_pad))) return rc;
+    if ((rc = dalloc(&b.acc64, g.n_pad))) return rc;
+    if ((rc = dalloc(&b.lvl, g.n_pad * 64))) return rc;
+    if ((rc = dalloc(&b.full, g.n_chunks))) return rc;
+  }
+  if (roots > b.root_cap) {
+    if (b.root_rows) (void)hipFree(b.root_rows);
+    if (b.slots) (void)hipFree(b.slots);
+    b.root_rows = b.slots = nullptr;
+    b.root_cap = 0;
+    if ((rc = dalloc(&b.root_rows, roots))) return rc;
+    if ((rc = dalloc(&b.slots, roots))) return rc;
+    b.root_cap = roots;
+  }
+  std::vector<unsigned long long> full((size_t)g.n_chunks, 0ull);
+  for (int32_t i = 0; i < g.num_graphs; ++i)
+    for (int64_t c = g.h_roff[i] / kC; c < g.h_roff[i + 1] / kC; ++c) full[c] = full_per_graph[i];
+  SS_HIP(hipMemcpyAsync(b.full, full.data(), sizeof(unsigned long long) * full.size(),
+                        hipMemcpyHostToDevice, st));
+  // the host vector must outlive the copy
+  SS_HIP(hipStreamSynchronize(st));
+  return SS_OK;
+}
+
 }  // namespace ss
 
 using namespace ss;
 
-struct ss_layout : public ss::Layout {};
-struct ss_graph : public ss::Graph {};
 
 extern "C" {
 
@@ -289,6 +527,9 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
   g->max_cl = L->max_cl;
   g->h_perm = L->perm;
   g->h_cl = L->cl;
+  g->num_graphs = 1;
+  g->h_voff = {0, (int64_t)L->n};
+  g->h_roff = {0, (int64_t)L->n_pad};
   g->h_degree.resize((size_t)L->n);
   for (int32_t o = 0; o < L->n; ++o) g->h_degree[o] = L->degree[L->perm[o]];
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -315,6 +556,10 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
     if (ee != hipSuccess) rc = hip_fail(ee, "upload layout");
   }
   if (!rc) rc = alloc_workspace(*g);
+  if (!rc) rc = dalloc(&g->d_voff, 2);
+  if (!rc && hipMemcpy(g->d_voff, g->h_voff.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice) !=
+                 hipSuccess)
+    rc = set_error(SS_EHIP, "upload graph offsets");
   if (rc) {
     release_graph(g);
     return rc;
@@ -392,185 +637,152 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   if ((int)s < 0 || (int)s > 3) return set_error(SS_EINVAL, "unknown semiring");
   if (parent && s != SS_SELMAX) return set_error(SS_EINVAL, "parent needs SS_SELMAX");
   if (real_val && s != SS_REAL) return set_error(SS_EINVAL, "real_val needs SS_REAL");
-  ss_bfs_opts def;
-  std::memset(&def, 0, sizeof(def));
-  def.size = sizeof(def);
-  def.slimwork = 2;
-  def.split_len = -1;
-  if (!o) o = &def;
-  if (o->size != sizeof(ss_bfs_opts)) return set_error(SS_EINVAL, "opts->size mismatch");
-  if (o->slimwork < 0 || o->slimwork > 2) return set_error(SS_EINVAL, "slimwork must be 0, 1 or 2");
   for (int32_t r = 0; r < num_roots; ++r)
     if (roots[r] < 0 || roots[r] >= g.n) return set_error(SS_EINVAL, "root out of range [0, n)");
-  const int waves = o->waves_per_group ? o->waves_per_group : g.tune.waves_per_group;
-  if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
-    return set_error(SS_EINVAL, "waves_per_group must be 1, 2, 4, 8 or 16");
-  int32_t split = o->split_len;
-  if (split < -1) return set_error(SS_EINVAL, "split_len must be >= -1");
-  if (split == -1) split = g.tune.split_len;
-  const int32_t pack = g.tune.pack_cols < 0 ? (split > 0 ? split : 0) : g.tune.pack_cols;
-  const int unroll = g.tune.unroll;
-  const int64_t max_groups = g.tune.max_groups;
-  const int64_t cap = (o->max_levels > 0) ? o->max_levels : (int64_t)g.n + 1;
-  if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
-  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS)) return set_error(SS_EINVAL, "bad flags");
-
+  ss_bfs_opts def = default_opts();
+  if (!o) o = &def;
   std::lock_guard<std::mutex> lock(g.mu);
   SS_HIP(hipSetDevice(g.device));
   hipStream_t st = static_cast<hipStream_t>(o->stream);
-  UnitList* ul = nullptr;
-  int rc = get_units(g, split, pack, &ul);
+  RunPlan plan;
+  int rc = plan_run(g, o, num_roots, (int64_t)g.n + 1, st, &plan);
   if (rc) return rc;
-  const bool timing = (o->flags & SS_STATS_TIME) != 0;
-  const int64_t lcap = o->level_cap;
-  const bool counting = (o->flags & SS_STATS_COUNTERS) && lcap > 0 && o->level_stats_out;
-  const int64_t words_per_root = (lcap + 1) * kCountSlots * kCountFields;
-  if (counting) {
-    rc = ensure_counters(g, words_per_root * num_roots);
-    if (rc) return rc;
-    rc = launch_fill_u64(g.ws.counters, 0ull, words_per_root * num_roots, st);
-    if (rc) return rc;
-  }
-  constexpr int kLookahead = 2;
-  size_t next_ev = 0;
-  std::vector<size_t> ev_first((size_t)num_roots, 0);
-  std::vector<int32_t> launches((size_t)num_roots, 0);
-  std::vector<int32_t> iters((size_t)num_roots, 0);
-
+  RunLog log((size_t)num_roots);
   for (int32_t r = 0; r < num_roots; ++r) {
-    g.run_id = (g.run_id >= 0x7FFFFFF0u) ? 1u : g.run_id + 1;
-    const uint32_t run = g.run_id;
-    const int32_t root_row = g.h_perm[roots[r]];
-    ev_first[r] = next_ev;
-    if (timing) {
-      hipEvent_t ev;
-      if ((rc = pool_event(g, next_ev++, &ev))) return rc;
-      SS_HIP(hipEventRecord(ev, st));
-    }
-    rc = launch_init(s, g, g.ws, root_row, st);
+    const uint32_t run = next_run_id(g);
+    if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[r]))) return rc;
+    rc = launch_init(s, g, g.ws, g.h_perm[roots[r]], st);
     if (rc) return rc;
-    LevelArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.col = g.d_col;
-    a.cs = g.d_cs;
-    a.cl = g.d_cl;
-    a.v = g.d_v;
-    a.deg = g.d_deg;
-    a.units = ul->d_units;
-    a.pieces = ul->d_pieces;
-    a.n_units = ul->count;
-    a.state = g.ws.state;
-    a.g = g.ws.g;
-    a.d = g.ws.d;
-    a.rv = g.ws.rv;
-    a.acc = g.ws.acc;
-    a.arrive = g.ws.arrive;
-    a.any = g.ws.any;
-    a.counters = counting ? g.ws.counters + words_per_root * r : nullptr;
-    a.report = g.ws.d_report;
-    a.run_id = run;
-    a.n_pad = (uint32_t)g.n_pad;
-    a.slimwork = o->slimwork;
-
-    int32_t launched = 0;
-    int32_t iterations = -1;
-    auto launch = [&](int32_t k) -> int {
-      a.level = k;
-      a.vin = (k & 1) ? g.ws.vec_a : g.ws.vec_b;
-      a.vout = (k & 1) ? g.ws.vec_b : g.ws.vec_a;
-      a.count_stats = (counting && k <= lcap) ? 1 : 0;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (timing) {
-        int pr;
-        if ((pr = pool_event(g, next_ev++, &e0))) return pr;
-        if ((pr = pool_event(g, next_ev++, &e1))) return pr;
-        SS_HIP(hipEventRecord(e0, st));
-      }
-      int lr = launch_level((int)s, waves, unroll, max_groups, a, st);
-      if (lr) return lr;
-      if (timing) SS_HIP(hipEventRecord(e1, st));
-      return SS_OK;
-    };
-    for (int32_t j = 1;; ++j) {
-      while (launched < j + kLookahead && launched <= cap) {
-        rc = launch(++launched);
-        if (rc) return rc;
-      }
-      bool found = false;
-      rc = wait_report(g, j, run, st, &found);
-      if (rc) return rc;
-      if (!found) {
-        iterations = j;
-        break;
-      }
-      if (j >= cap) {
-        (void)hipStreamSynchronize(st);
-        return set_error(SS_EITER, "level cap reached before the BFS finished");
-      }
-    }
-    launches[r] = launched;
-    iters[r] = iterations;
-    if (o->iterations_out) o->iterations_out[r] = iterations;
+    LevelArgs a = base_args(g, plan, o, run, r);
+    rc = run_levels(g, plan, (int)s, a, g.ws.vec_a, g.ws.vec_b, st, &log, r);
+    if (rc) return rc;
+    if (o->iterations_out) o->iterations_out[r] = log.iters[r];
     rc = launch_finalise(s, g, g.ws, dist + (int64_t)r * g.n,
                          parent ? parent + (int64_t)r * g.n : nullptr,
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
-    if (timing) {
-      hipEvent_t ev;
-      if ((rc = pool_event(g, next_ev++, &ev))) return rc;
-      SS_HIP(hipEventRecord(ev, st));
-    }
+    if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
   }
+  return collect_stats(g, o, plan, num_roots, log, st);
+}
 
-  const bool want_levels = o->level_stats_out && lcap > 0;
-  if (!(timing || counting || o->run_stats_out || want_levels)) return SS_OK;
-  SS_HIP(hipStreamSynchronize(st));
-  std::vector<unsigned long long> h;
-  if (counting) {
-    h.resize((size_t)(words_per_root * num_roots));
-    SS_HIP(hipMemcpy(h.data(), g.ws.counters, sizeof(unsigned long long) * h.size(),
-                     hipMemcpyDeviceToHost));
-  }
-  for (int32_t r = 0; r < num_roots; ++r) {
-    float kernel_ms = 0.f, bfs_ms = 0.f;
-    std::vector<float> lvl_ms((size_t)launches[r], 0.f);
-    if (timing) {
-      const size_t e = ev_first[r];
-      auto ev = [&](size_t i) { return static_cast<hipEvent_t>(g.ev_pool[i]); };
-      for (int32_t k = 0; k < launches[r]; ++k) {
-        float ms = 0.f;
-        SS_HIP(hipEventElapsedTime(&ms, ev(e + 1 + 2 * k), ev(e + 2 + 2 * k)));
-        lvl_ms[k] = ms;
-        kernel_ms += ms;
-      }
-      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1 + 2 * launches[r])));
-    }
-    if (o->run_stats_out) {
-      ss_run_stats& rs = o->run_stats_out[r];
-      rs.iterations = iters[r];
-      rs.launches = launches[r];
-      rs.kernel_ms = kernel_ms;
-      rs.bfs_ms = bfs_ms;
-    }
-    if (want_levels) {
-      for (int64_t k = 1; k <= lcap; ++k) {
-        ss_level_stats& ls = o->level_stats_out[r * lcap + (k - 1)];
-        std::memset(&ls, 0, sizeof(ls));
-        if (k > iters[r]) continue;
-        ls.ms = timing ? lvl_ms[k - 1] : 0.f;
-        if (counting) {
-          const unsigned long long* base = h.data() + words_per_root * r;
-          for (int q = 0; q < kCountSlots; ++q) {
-            const unsigned long long* f = base + (k * kCountSlots + q) * kCountFields;
-            ls.discovered += (int64_t)f[0];
-            ls.active_chunks += (int64_t)f[1];
-            ls.active_cells += (int64_t)f[2];
-            ls.max_active_cl = std::max<int64_t>(ls.max_active_cl, (int64_t)f[3]);
-          }
-        }
-      }
+int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss_bfs_opts* o,
+                       int32_t* dist) {
+  if (!gp) return set_error(SS_EINVAL, "graph is NULL");
+  Graph& g = *gp;
+  if (rpg < 1 || rpg > 64) return set_error(SS_EINVAL, "roots_per_graph must be in 1..64");
+  if (!roots || !dist) return set_error(SS_EINVAL, "roots and dist are required");
+  std::vector<int32_t> root_rows, slots;
+  std::vector<unsigned long long> full((size_t)g.num_graphs, 0ull);
+  for (int32_t i = 0; i < g.num_graphs; ++i) {
+    const int64_t ni = g.h_voff[i + 1] - g.h_voff[i];
+    for (int32_t b = 0; b < rpg; ++b) {
+      const int32_t r = roots[(int64_t)i * rpg + b];
+      if (r == -1) continue;
+      if (r < 0 || r >= ni) return set_error(SS_EINVAL, "root out of range of its graph");
+      root_rows.push_back(g.h_perm[g.h_voff[i] + r]);
+      slots.push_back(b);
+      full[i] |= 1ull << b;
     }
   }
+  ss_bfs_opts def = default_opts();
+  if (!o) o = &def;
+  std::lock_guard<std::mutex> lock(g.mu);
+  SS_HIP(hipSetDevice(g.device));
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  RunPlan plan;
+  int rc = plan_run(g, o, 1, std::min<int64_t>((int64_t)g.n + 1, 65534), st, &plan);
+  if (rc) return rc;
+  if ((rc = ensure_batch_workspace(g, (int64_t)root_rows.size(), full, st))) return rc;
+  BatchWorkspace& bw = g.bw;
+  if (!root_rows.empty()) {
+    SS_HIP(hipMemcpyAsync(bw.root_rows, root_rows.data(), sizeof(int32_t) * root_rows.size(),
+                          hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemcpyAsync(bw.slots, slots.data(), sizeof(int32_t) * slots.size(),
+                          hipMemcpyHostToDevice, st));
+  }
+  RunLog log(1);
+  const uint32_t run = next_run_id(g);
+  if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[0]))) return rc;
+  rc = launch_batch_init(g, bw, (int32_t)root_rows.size(), st);
+  if (rc) return rc;
+  LevelArgs a = base_args(g, plan, o, run, 0);
+  a.acc64 = bw.acc64;
+  a.vis = bw.vis;
+  a.full = bw.full;
+  a.lvl = bw.lvl;
+  rc = run_levels(g, plan, kBatchSemiring, a, bw.fa, bw.fb, st, &log, 0);
+  if (rc) return rc;
+  if (o->iterations_out) o->iterations_out[0] = log.iters[0];
+  rc = launch_batch_finalise(g, bw, rpg, dist, st);
+  if (rc) return rc;
+  if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
+  return collect_stats(g, o, plan, 1, log, st);
+}
+
+int slimsell_graph_parts(const ss_graph* g, int32_t* num_graphs, int64_t* n_per_graph,
+                         int64_t* vertex_offset) {
+  if (!g || !num_graphs) return set_error(SS_EINVAL, "NULL argument");
+  *num_graphs = g->num_graphs;
+  for (int32_t i = 0; i < g->num_graphs; ++i) {
+    if (n_per_graph) n_per_graph[i] = g->h_voff[i + 1] - g->h_voff[i];
+    if (vertex_offset) vertex_offset[i] = g->h_voff[i];
+  }
+  return SS_OK;
+}
+
+int slimsell_build_multi(int32_t num_graphs, const int64_t* edge_offsets, const int32_t* src,
+                         const int32_t* dst, const int32_t* n_per_graph, int32_t C,
+                         int32_t sigma, void* stream, ss_graph** out) {
+  if (!out) return set_error(SS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (num_graphs < 1 || !edge_offsets || !n_per_graph)
+    return set_error(SS_EINVAL, "num_graphs >= 1 with edge_offsets and n_per_graph required");
+  ss_layout U;
+  std::vector<int64_t> voff((size_t)num_graphs + 1, 0), roff((size_t)num_graphs + 1, 0);
+  for (int32_t i = 0; i < num_graphs; ++i) {
+    if (n_per_graph[i] < 1) return set_error(SS_EINVAL, "every graph needs n >= 1");
+    const int64_t e0 = edge_offsets[i], e1 = edge_offsets[i + 1];
+    if (e0 < 0 || e1 < e0) return set_error(SS_EINVAL, "edge_offsets must be non-decreasing");
+    Layout* L = nullptr;
+    int rc = build_layout(src ? src + e0 : nullptr, dst ? dst + e0 : nullptr, e1 - e0,
+                          n_per_graph[i], C, sigma == 0 ? 0 : std::min(sigma, n_per_graph[i]), &L);
+    if (rc) return rc;
+    voff[i + 1] = voff[i] + L->n;
+    roff[i + 1] = roff[i] + L->n_pad;
+    if (roff[i + 1] > INT32_MAX) { delete L; return set_error(SS_EINVAL, "union too large"); }
+    const int32_t ro = (int32_t)roff[i];
+    const int64_t cell0 = U.cells;
+    for (int32_t c : L->col) U.col.push_back(c < 0 ? -1 : c + ro);
+    if (U.cs.empty()) U.cs.push_back(0);
+    for (int64_t k = 1; k < (int64_t)L->cs.size(); ++k) U.cs.push_back(cell0 + L->cs[k]);
+    U.cl.insert(U.cl.end(), L->cl.begin(), L->cl.end());
+    for (int32_t x : L->v) U.v.push_back(x == 0 ? 0 : (int32_t)(x + voff[i]));
+    for (int32_t r : L->perm) U.perm.push_back(r + ro);
+    U.degree.insert(U.degree.end(), L->degree.begin(), L->degree.end());
+    U.cells += L->cells;
+    U.entries += L->entries;
+    U.max_cl = std::max(U.max_cl, L->max_cl);
+    delete L;
+  }
+  U.n = (int32_t)voff[num_graphs];
+  U.n_pad = (int32_t)roff[num_graphs];
+  U.n_chunks = U.n_pad / kC;
+  U.sigma = sigma;
+  ss_graph* g = nullptr;
+  int rc = slimsell_build_from_layout(&U, stream, &g);
+  if (rc) return rc;
+  g->num_graphs = num_graphs;
+  g->h_voff = voff;
+  g->h_roff = roff;
+  if (g->d_voff) (void)hipFree(g->d_voff);
+  g->d_voff = nullptr;
+  rc = dalloc(&g->d_voff, num_graphs + 1);
+  if (!rc && hipMemcpy(g->d_voff, voff.data(), sizeof(int64_t) * voff.size(),
+                       hipMemcpyHostToDevice) != hipSuccess)
+    rc = set_error(SS_EHIP, "upload graph offsets");
+  if (rc) { slimsell_free(g); return rc; }
+  *out = g;
   return SS_OK;
 }
 

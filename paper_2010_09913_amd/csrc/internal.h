@@ -69,6 +69,22 @@ struct Workspace {
   uint64_t* d_report = nullptr;  // device view of h_report
 };
 
+constexpr int kBatchSemiring = 4;  // level-kernel policy id of the batched SpMM
+
+// Device workspace of the batched SpMM (allocated on first use).
+struct BatchWorkspace {
+  int64_t n_pad = 0;
+  unsigned long long* vis = nullptr;    // [n_pad] roots that reached the row
+  unsigned long long* fa = nullptr;     // [n_pad] frontier masks, buffer A
+  unsigned long long* fb = nullptr;     // [n_pad] frontier masks, buffer B
+  unsigned long long* acc64 = nullptr;  // [n_pad] SlimChunk partial combine
+  uint16_t* lvl = nullptr;              // [n_pad * 64] level of each (row, slot)
+  unsigned long long* full = nullptr;   // [n_chunks] slots in use by the chunk's graph
+  int32_t* root_rows = nullptr;         // [capacity] root row of each used slot
+  int32_t* slots = nullptr;             // [capacity] slot of each used root
+  int64_t root_cap = 0;
+};
+
 constexpr int kCountSlots = 16;  // counter atomics are spread over this many slots
 constexpr int kCountFields = 4;  // discovered, active chunks, active columns, max active cl
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
@@ -90,6 +106,12 @@ struct Graph {
   std::vector<void*> ev_pool;     // hipEvent_t pool for SS_STATS_TIME
   std::map<std::pair<int32_t, int32_t>, UnitList> units;  // by (split_len, pack_cols)
   Workspace ws;
+  BatchWorkspace bw;
+  // multi-graph description (one graph: num_graphs = 1, voff = {0, n})
+  int32_t num_graphs = 1;
+  std::vector<int64_t> h_voff;    // [num_graphs + 1] union-ID offset of each graph
+  std::vector<int64_t> h_roff;    // [num_graphs + 1] row offset of each graph
+  int64_t* d_voff = nullptr;
   uint32_t run_id = 0;
   ss_tune tune{256, 1, 8, 0, 0, 0};  // launch configuration (slimsell_tune_set / autotune)
   std::mutex mu;
@@ -117,6 +139,11 @@ struct LevelArgs {
   // per-level counters of this root: [(level * kCountSlots + slot) * kCountFields + field]
   unsigned long long* counters;
   uint64_t* report;
+  // batched SpMM only
+  unsigned long long* acc64;
+  unsigned long long* vis;
+  const unsigned long long* full;
+  uint16_t* lvl;
   uint32_t run_id;
   uint32_t n_pad;    // rows (multiple of 64)
   int32_t level;     // k >= 1
@@ -131,6 +158,13 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
 int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,
                     int32_t* parent, float* real_val, void* stream);
 int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream);
+int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, void* stream);
+int launch_batch_finalise(const Graph& g, const BatchWorkspace& b, int32_t rpg, int32_t* dist,
+                          void* stream);
 int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count, void* stream);
 
 }  // namespace ss
+
+// The opaque ABI types are the internal structures.
+struct ss_layout : public ss::Layout {};
+struct ss_graph : public ss::Graph {};

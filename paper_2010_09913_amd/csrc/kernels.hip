@@ -78,8 +78,10 @@ struct Tropical {
     }
     return acc;
   }
-  __device__ static void atomic_combine(int32_t* p, Acc v) { keep(atomicMin(p, v)); }
-  __device__ static Acc take(int32_t* p) { return atomicExch(p, kInf); }
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep(atomicMin(&a.acc[row], v));
+  }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc[row], kInf); }
   // f_k^row = min(f_{k-1}^row, acc): the zero diagonal of A' keeps the old value
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const int32_t own = a.state[row];
@@ -108,10 +110,12 @@ struct Real {
     for (int t = 0; t < U; ++t) acc += y[t];
     return acc;
   }
-  __device__ static void atomic_combine(int32_t* p, Acc v) {
-    keep(__float_as_int(atomicAdd(reinterpret_cast<float*>(p), v)));
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep(__float_as_int(atomicAdd(reinterpret_cast<float*>(&a.acc[row]), v)));
   }
-  __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<float*>(p), 0.0f); }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) {
+    return atomicExch(reinterpret_cast<float*>(&a.acc[row]), 0.0f);
+  }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const uint8_t gg = a.g[row];
     const bool fresh = (acc * (float)gg) != 0.0f;
@@ -141,10 +145,12 @@ struct Boolean {
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
   }
-  __device__ static void atomic_combine(int32_t* p, Acc v) {
-    keep((int32_t)atomicOr(reinterpret_cast<uint32_t*>(p), v));
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep((int32_t)atomicOr(reinterpret_cast<uint32_t*>(&a.acc[row]), v));
   }
-  __device__ static Acc take(int32_t* p) { return atomicExch(reinterpret_cast<uint32_t*>(p), 0u); }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) {
+    return atomicExch(reinterpret_cast<uint32_t*>(&a.acc[row]), 0u);
+  }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (acc != 0u) && (a.g[row] != 0);
     static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
@@ -190,8 +196,10 @@ struct SelMax {
     for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
     return acc;
   }
-  __device__ static void atomic_combine(int32_t* p, Acc v) { keep(atomicMax(p, v)); }
-  __device__ static Acc take(int32_t* p) { return atomicExch(p, 0); }
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep(atomicMax(&a.acc[row], v));
+  }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc[row], 0); }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (a.state[row] == 0) && (acc != 0);
     if (fresh) {
@@ -203,6 +211,50 @@ struct SelMax {
   __device__ static void publish(const LevelArgs& a, int32_t chunk, uint64_t mask, int lane) {
     if (lane == 0) static_cast<uint64_t*>(a.vout)[chunk] = mask;
   }
+};
+
+// Batched boolean SpMM (multi-source BFS): each row carries a 64-bit mask,
+// bit b for root slot b.  X = OR over the row's neighbours of F_{k-1};
+// new = X & ~visited; visited |= new; F_k = new; the level of every new bit is
+// recorded in the row's 64 x 16-bit level record.  A row is final once every
+// slot its graph uses has reached it.
+struct Batch {
+  using Acc = unsigned long long;
+  __device__ static Acc identity() { return 0ull; }
+  __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 8u); }
+  __device__ static bool live(const LevelArgs& a, int32_t row) {
+    const Acc full = a.full[row / kC];
+    return (a.vis[row] & full) != full;
+  }
+  template <int U>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+    Acc y[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off_of(c[t], 3), 0, 0);
+      y[t] = ((Acc)w[1] << 32) | (Acc)w[0];
+    }
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc |= y[t];
+    return acc;
+  }
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep((int32_t)atomicOr(&a.acc64[row], v));
+  }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc64[row], 0ull); }
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+    const Acc seen = a.vis[row];
+    Acc fresh = acc & ~seen & a.full[row / kC];
+    static_cast<Acc*>(a.vout)[row] = fresh;
+    if (fresh) {
+      a.vis[row] = seen | fresh;
+      uint16_t* lv = a.lvl + (int64_t)row * 64;
+      const uint16_t k = (uint16_t)a.level;
+      for (Acc m = fresh; m; m &= m - 1) lv[__ffsll((long long)m) - 1] = k;
+    }
+    return fresh != 0ull;
+  }
+  __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
 };
 
 // ---------------------------------------------------------- level kernel ---
@@ -312,13 +364,13 @@ __global__ void level_kernel(LevelArgs a) {
         // Pieces exchange data only through device-scope atomics: each piece's
         // combine has completed before its arrival is counted, so the last
         // arrival's exchange sees every piece.
-        S::atomic_combine(&a.acc[row], acc);
+        S::atomic_combine(a, row, acc);
         wait_memory();
         int last = 0;
         if (lane == 0) last = (atomicAdd(&a.arrive[c], 1) == npieces - 1);
         last = __shfl(last, 0);
         if (last) {
-          acc = S::take(&a.acc[row]);
+          acc = S::take(a, row);
           if (lane == 0) a.arrive[c] = 0;
           found += finish_rows<S>(a, c, row, acc, lane);
         }
@@ -402,6 +454,50 @@ __global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* s
   if (SEMI == SS_REAL && real_val) real_val[o] = rv[row];
 }
 
+// Batched level 0: every row starts with an empty mask (phantom rows are
+// final); then each used root slot sets its bit and level 0 at its root row.
+__global__ void batch_init_kernel(int32_t n_pad, int64_t n_chunks, const int32_t* v,
+                                  unsigned long long* vis, unsigned long long* fa,
+                                  unsigned long long* acc64, int32_t* arrive) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_chunks) arrive[r] = 0;
+  if (r >= n_pad) return;
+  vis[r] = (v[r] == 0) ? ~0ull : 0ull;
+  fa[r] = 0ull;
+  acc64[r] = 0ull;
+}
+
+__global__ void batch_roots_kernel(int32_t count, const int32_t* root_rows, const int32_t* slots,
+                                   unsigned long long* vis, unsigned long long* fa,
+                                   uint16_t* lvl) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int32_t row = root_rows[i];
+  const unsigned long long bit = 1ull << slots[i];
+  atomicOr(&vis[row], bit);
+  atomicOr(&fa[row], bit);
+  lvl[(int64_t)row * 64 + slots[i]] = 0;
+}
+
+// Row records -> dist[graph block][slot][vertex]; unreached and unused = -1.
+__global__ void batch_finalise_kernel(int64_t n, int32_t num_graphs, const int64_t* voff,
+                                      const int32_t* perm, const unsigned long long* vis,
+                                      const uint16_t* lvl, int32_t rpg, int32_t* dist) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  int32_t lo = 0, hi = num_graphs - 1;  // graph of o: last i with voff[i] <= o
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) / 2;
+    if (voff[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  const int64_t base = voff[lo], ni = voff[lo + 1] - base;
+  const int32_t row = perm[o];
+  const unsigned long long seen = vis[row];
+  const uint16_t* lv = lvl + (int64_t)row * 64;
+  int32_t* out = dist + (int64_t)rpg * base + (o - base);
+  for (int32_t b = 0; b < rpg; ++b) out[(int64_t)b * ni] = ((seen >> b) & 1ull) ? (int32_t)lv[b] : -1;
+}
+
 template <class T>
 __global__ void fill_kernel(T* p, T value, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -464,6 +560,7 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
     case SS_REAL: launch_level_t<Real>(waves, unroll, grid, a, st); break;
     case SS_BOOLEAN: launch_level_t<Boolean>(waves, unroll, grid, a, st); break;
     case SS_SELMAX: launch_level_t<SelMax>(waves, unroll, grid, a, st); break;
+    case kBatchSemiring: launch_level_t<Batch>(waves, unroll, grid, a, st); break;
     default: return set_error(SS_EINVAL, "unknown semiring");
   }
   return check_launch("level_kernel");
@@ -493,6 +590,25 @@ int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream) {
   if (blocks > 4096) blocks = 4096;
   fill_kernel<int32_t><<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(p, value, count);
   return check_launch("fill_kernel");
+}
+
+int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  batch_init_kernel<<<blocks_for(g.n_pad, 256), 256, 0, st>>>(g.n_pad, g.n_chunks, g.d_v, b.vis,
+                                                              b.fa, b.acc64, g.ws.arrive);
+  int rc = check_launch("batch_init_kernel");
+  if (rc || count == 0) return rc;
+  batch_roots_kernel<<<blocks_for(count, 256), 256, 0, st>>>(count, b.root_rows, b.slots, b.vis,
+                                                             b.fa, b.lvl);
+  return check_launch("batch_roots_kernel");
+}
+
+int launch_batch_finalise(const Graph& g, const BatchWorkspace& b, int32_t rpg, int32_t* dist,
+                          void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  batch_finalise_kernel<<<blocks_for(g.n, 256), 256, 0, st>>>(
+      g.n, g.num_graphs, g.d_voff, g.d_perm, b.vis, b.lvl, rpg, dist);
+  return check_launch("batch_finalise_kernel");
 }
 
 int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count,
