@@ -111,6 +111,107 @@ def summarise(out, roots, semi, n, nonempty_chunks, steps):
     return s
 
 
+def _events_ms(torch, fn, reps=3):
+    """Median wall time of fn() on the current stream, by torch events."""
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out))
+
+
+def bench_batched(ss, graphgen, torch) -> dict:
+    """64 roots in one boolean SpMM vs 64 plain runs (R-MAT s21), and 256
+    Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], mean degree 8-64) in one
+    union solved by one level loop."""
+    e = graphgen.rmat(21, 16, seed=1)
+    roots = graphgen.pick_roots(e, 64, seed=1004)
+    G = ss.Graph.from_edgelist(e, sigma=0)
+    deg = torch.from_numpy(G.degrees().astype(np.int64)).cuda()
+    G.bfs_batch(roots[None, :])
+    t_batch = _events_ms(torch, lambda: G.bfs_batch(roots[None, :]))
+    dist, _, _, _ = G.bfs_batch(roots[None, :])
+    d = dist.view(64, -1)
+    m_cc = float(((d >= 0).to(torch.int64) * deg[None, :]).sum() // 2)
+    G.bfs(roots, "selmax")
+    t_plain = _events_ms(torch, lambda: G.bfs(roots, "selmax"), reps=2)
+    G.bfs(roots, "boolean")
+    t_bool = _events_ms(torch, lambda: G.bfs(roots, "boolean"), reps=2)
+    G.close()
+    log(f"batched s21: {t_batch:.2f} ms vs 64 sel-max {t_plain:.2f} ms, boolean {t_bool:.2f} ms")
+    out = {"rmat_s21_64_roots": {
+        "batched_ms": round(t_batch, 3), "plain_selmax_ms": round(t_plain, 3),
+        "plain_boolean_ms": round(t_bool, 3), "gteps_batched": round(m_cc / t_batch / 1e6, 3),
+        "gteps_plain_selmax": round(m_cc / t_plain / 1e6, 3),
+        "speedup_vs_selmax": round(t_plain / t_batch, 2)}}
+    t = time.perf_counter()
+    graphs = graphgen.er_set(256, seed=3)
+    Gm = ss.Graph.from_many(graphs)
+    build = time.perf_counter() - t
+    R = np.full((256, 64), -1, np.int32)
+    for i, g in enumerate(graphs):
+        rr = graphgen.pick_roots(g, 64, seed=5000 + i)
+        R[i, :len(rr)] = rr
+    Gm.bfs_batch(R)
+    t_many = _events_ms(torch, lambda: Gm.bfs_batch(R))
+    dist, iters, _, _ = Gm.bfs_batch(R)
+    ns, off = Gm.parts()
+    degm = torch.from_numpy(Gm.degrees().astype(np.int64)).cuda()
+    edges = 0.0
+    dd = dist
+    for i in range(256):
+        blk = dd[64 * off[i]: 64 * (off[i] + ns[i])].view(64, int(ns[i]))
+        edges += float(((blk >= 0).to(torch.int64) * degm[off[i]:off[i] + ns[i]][None, :]).sum() // 2)
+    Gm.close()
+    log(f"256 ER graphs: {t_many:.2f} ms, {iters} levels, build {build:.1f}s")
+    out["er_256_graphs"] = {"vertices": int(ns.sum()), "roots": int((R >= 0).sum()),
+                            "levels": int(iters), "batched_ms": round(t_many, 3),
+                            "gteps": round(edges / t_many / 1e6, 3),
+                            "build_s": round(build, 1)}
+    return out
+
+
+def bench_learned(ss, graphgen, torch) -> dict:
+    """Learned per-level schedule vs the fixed heuristic vs each forced variant,
+    total BFS time over the roots (R-MAT s24; 4096^2 grid with 5% of edges
+    removed).  The model was trained on timings of the scale-12..22 graphs."""
+    from paper_2010_09913_amd import scheduler
+    path = scheduler.DEFAULT_MODEL
+    if not os.path.exists(path):
+        return {"skipped": "no trained model at " + os.path.relpath(path, ROOT)}
+    ss.sched_load(np.load(path))
+    out = {"model": os.path.relpath(path, ROOT)}
+    cases = [("rmat_s24", lambda: graphgen.rmat(24, 16, seed=1), 8, 1005, None),
+             ("grid_4096_cut5", lambda: graphgen.grid(4096, 4096, 0.05, seed=5), 4, 1005, 1)]
+    for name, make, nroots, seed, slow_roots in cases:
+        e = make()
+        roots = graphgen.pick_roots(e, nroots, seed=seed)
+        G = ss.Graph.from_edgelist(e, sigma=0)
+        res = {}
+        for mode in ["learned", "heuristic", "pull", "pull-split256", "pull-split1024", "push"]:
+            rr = roots
+            if slow_roots and mode.startswith("pull"):
+                rr = roots[:slow_roots]   # pull-only on the grid is O(levels x n): few roots
+            G.bfs([int(rr[0])], "selmax", schedule=mode)
+            tot = 0.0
+            for r in rr:
+                x = G.bfs([int(r)], "selmax", schedule=mode, timing=True)
+                tot += float(x.runs["bfs_ms"][0])
+            res[mode] = round(tot / len(rr), 3)
+            log(f"{name} {mode}: {tot / len(rr):.2f} ms per BFS")
+        G.close()
+        res["learned_vs_heuristic"] = round(res["heuristic"] / res["learned"], 3)
+        res["best_forced"] = min(("pull", "pull-split256", "pull-split1024", "push"),
+                                 key=lambda m: res[m])
+        out[name] = {"ms_per_bfs": res, "roots": int(len(roots))}
+    ss.sched_clear()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +227,11 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true", help="skip the split sweep and ER graph")
     ap.add_argument("--only-timed", action="store_true",
                     help="warm-up and timed steps only (for profiler runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched SpMM comparison")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-schedule comparison (R-MAT s24, 4096^2 grid)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -141,6 +247,15 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4,
+                          "copy_probe_bytes_written": dst.numel() * 4, "launches": 4}))
+        return 0
     semi = args.semiring
 
     t = time.perf_counter()
@@ -220,6 +335,11 @@ def main() -> int:
                                    "gteps_hmean": round(se["gteps_hmean"], 4),
                                    "frac": round(se.get("frac", 0.0), 4)}
         Ge.close()
+
+    if not args.only_timed and not args.no_batch:
+        result["batched"] = bench_batched(ss, graphgen, torch)
+    if not args.only_timed and not args.no_learned:
+        result["learned_schedule"] = bench_learned(ss, graphgen, torch)
 
     if not args.no_cpu and not args.only_timed:
         import oracle

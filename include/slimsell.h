@@ -166,6 +166,11 @@ int slimsell_graph_degrees(const ss_graph* g, int32_t* degree);
  *   pack_cols       : chunks shorter than split_len are packed into runs of
  *                     at most this many columns per work unit; 0 = one chunk
  *                     per unit; -1 = split_len.
+ *   lds_kib         : KiB of the gathered vector's prefix (the highest-degree
+ *                     rows under a full sort) that each workgroup stages in
+ *                     LDS once per level: 0, 16, 32 or 64.  Pays off with a
+ *                     capped grid (max_groups), where each workgroup serves
+ *                     many work units.
  */
 typedef struct {
   int32_t split_len;
@@ -173,7 +178,7 @@ typedef struct {
   int32_t unroll;
   int32_t max_groups;
   int32_t pack_cols;
-  int32_t pad0;
+  int32_t lds_kib;
 } ss_tune;
 
 /* Set / read the graph's launch configuration.  SS_EINVAL on a bad field. */
@@ -184,8 +189,8 @@ int slimsell_tune_get(const ss_graph* g, ss_tune* tune);
  * Autotuner: measures the level kernel's launch configuration on this graph
  * and stores the fastest in it (slimsell_tune_set).  Coordinate descent over
  * split_len {0, 64, ..., 4096}, waves_per_group {1, ..., 16}, unroll
- * {4, 8, 16}, max_groups {0, 1024, 4096} and pack_cols {0, 32, 128}, two
- * passes; each configuration is timed (events, init to finalise) over the
+ * {4, 8, 16}, max_groups {0, 1024, 4096}, pack_cols {0, 32, 128} and
+ * lds_kib {0, 32, 64}, two passes; each configuration is timed (events, init to finalise) over the
  * given roots, median of `repeats`.  Results are cached per graph class
  * (semiring, batched, log2 n, mean degree, degree skew) for the process.
  * Results of BFS calls do not depend on the configuration.
@@ -225,12 +230,14 @@ void slimsell_free(ss_graph* g);
 
 /* Per-level record (see ss_bfs_opts.flags). */
 typedef struct {
-  int64_t discovered;    /* vertices that entered the frontier at this level */
-  int64_t active_chunks; /* chunks processed, i.e. not skipped by SlimWork */
-  int64_t active_cells;  /* col cells streamed (64 x columns of the processed pieces) */
-  int64_t max_active_cl; /* longest processed chunk, in columns */
-  float ms;              /* kernel time of the level (events), 0 if not timed */
-  int32_t pad0;
+  int64_t discovered;     /* vertices that entered the frontier at this level */
+  int64_t frontier_edges; /* sum of their degrees */
+  int64_t active_chunks;  /* chunks processed by a pull level (not skipped by SlimWork) */
+  int64_t active_cells;   /* col cells read: 64 x columns swept (pull) or cells of the
+                             frontier rows (push) */
+  int64_t max_active_cl;  /* longest processed chunk, in columns */
+  float ms;               /* kernel time of the level (events), 0 if not timed */
+  int32_t variant;        /* variant run by a scheduled level, -1 otherwise */
 } ss_level_stats;
 
 /* Per-root record (see ss_bfs_opts.flags). */
@@ -243,6 +250,12 @@ typedef struct {
 
 #define SS_STATS_TIME 1     /* hipEvents around every level kernel and every BFS */
 #define SS_STATS_COUNTERS 2 /* fused per-level counters (a few atomics per wavefront) */
+/* Run all levels of a BFS in one cooperative (persistent) kernel launch with a
+ * device-wide barrier between levels, instead of one launch per level: one
+ * 1024-thread workgroup per compute unit (capped by the graph's max_groups).
+ * Needs schedule = 0.  Per-level times are not available in this mode; a
+ * barrier that waits more than 5 s is reported as SS_EHIP. */
+#define SS_RUN_PERSISTENT 4
 
 /*
  * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
@@ -258,15 +271,24 @@ typedef struct {
  *                     this, -1 = the graph's tuned value (see slimsell_autotune),
  *                     falling back to the built-in default.
  *   waves_per_group : wavefronts per workgroup (1, 2, 4, 8 or 16; 0 = default).
- *   schedule        : 0 = fixed, 1 = learned per-level variant choice
- *                     (slimsell_sched_load), falling back to the fixed
- *                     heuristic when no valid model is loaded.
+ *   schedule        : per-level variant choice among {pull without split,
+ *                     pull split 256, pull split 1024, push from the frontier}:
+ *                     0 = none (every level pulls with the graph's configuration);
+ *                     1 = learned (slimsell_sched_load), falling back to the fixed
+ *                         heuristic when no model is loaded or its scores are
+ *                         not finite;
+ *                     2 = the fixed heuristic: pull (with the graph's split
+ *                         length) once the frontier's edges exceed 1/14 of the
+ *                         edges not yet discovered, push before (the direction
+ *                         rule of Beamer et al., alpha = 14);
+ *                     3..6 = force variant 0..3 on every level.
+ *                     Scheduling needs slimwork = 2.
  *   max_levels      : cap on SpMV iterations (0 = n + 1).  Reaching it
  *                     returns SS_EITER.
  *   stream          : hipStream_t.
  *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
  *                     (eccentricity + 1; the last one discovers nothing).
- *   flags           : SS_STATS_TIME and/or SS_STATS_COUNTERS.
+ *   flags           : SS_STATS_TIME, SS_STATS_COUNTERS, SS_RUN_PERSISTENT.
  *   level_cap       : levels per root recorded in level_stats_out.
  *   level_stats_out : host ss_level_stats[num_roots * level_cap] or NULL;
  *                     entry [r * level_cap + k - 1] describes level k of root r.
@@ -306,6 +328,48 @@ typedef struct {
  */
 int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiring s,
                  const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
+
+/* ------------------------------------------------------- learned schedule */
+
+/*
+ * Scheduler model (not in the paper): an FP32 MLP 6 -> 32 -> 32 -> 4 with ReLU
+ * that maps six features of the previous level's frontier to the predicted
+ * log-time of each variant; the smallest wins.  Parameter layout (1412
+ * floats): W1[32][6], b1[32], W2[32][32], b2[32], W3[4][32], b3[4].
+ * Features, in order: log2(1+n_f)/log2 n; log2(1+m_f)/log2(1+2m);
+ * log2(1+m_u)/log2(1+2m); n_u/n; clamp(log2((1+n_f)/(1+n_f,prev))/8, +-1);
+ * log2(1+2m/n)/8 -- n_f, m_f: vertices and edges of the frontier; n_u, m_u:
+ * vertices and edges not yet discovered; m: undirected edges.
+ */
+#define SS_SCHED_PARAMS 1412
+#define SS_SCHED_FEATURES 6
+#define SS_SCHED_VARIANTS 4
+
+/* Install the process-wide model (host float[1412]); non-finite values are
+ * accepted, and the fixed heuristic then takes over at run time. */
+int slimsell_sched_load(const float* weights, int64_t count);
+/* Remove the model (learned scheduling then uses the fixed heuristic). */
+int slimsell_sched_clear(void);
+/* Per-level record of the last scheduled run on g: host float[cap][12] =
+ * 6 features, 4 scores (0 without a model), chosen variant, level. */
+int slimsell_sched_log(const ss_graph* g, float* out, int32_t cap, int32_t* levels);
+
+/*
+ * Model training on the GPU.  Loss: mean squared error over the N x 4
+ * targets; optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8), full batch.
+ *   x       : host float[N][6] features; y: host float[N][4] targets.
+ *   init    : host float[1412] starting weights, or NULL for a seeded
+ *             He-uniform start (seed).
+ * slimsell_sched_grad evaluates the loss and its gradient once;
+ * slimsell_sched_forward the scores.  Outputs are host arrays.
+ */
+int slimsell_sched_grad(const float* weights, const float* x, const float* y, int64_t n,
+                        float* grad, float* loss, void* stream);
+int slimsell_sched_forward(const float* weights, const float* x, int64_t n, float* scores,
+                           void* stream);
+int slimsell_sched_train(const float* x, const float* y, int64_t n, int32_t steps, float lr,
+                         uint64_t seed, const float* init, float* weights_out, float* loss_out,
+                         void* stream);
 
 /*
  * Batched BFS as a boolean SpMM (not in the paper; multi-source BFS): every

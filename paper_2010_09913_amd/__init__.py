@@ -90,7 +90,11 @@ def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
         lib.slimsell_layout_free(h)
 
 
-LEVEL_FIELDS = ("discovered", "active_chunks", "active_cells", "max_active_cl", "ms")
+LEVEL_FIELDS = ("discovered", "frontier_edges", "active_chunks", "active_cells",
+                "max_active_cl", "ms", "variant")
+VARIANTS = ("pull", "pull-split256", "pull-split1024", "push")
+SCHEDULES = {"none": 0, "learned": 1, "heuristic": 2, "pull": 3, "pull-split256": 4,
+             "pull-split1024": 5, "push": 6}
 RUN_FIELDS = ("iterations", "launches", "kernel_ms", "bfs_ms")
 
 
@@ -178,7 +182,7 @@ class Graph:
         check(_native.load().slimsell_graph_degrees(self._h, _p32(out)))
         return out
 
-    TUNE_FIELDS = ("split_len", "waves_per_group", "unroll", "max_groups", "pack_cols")
+    TUNE_FIELDS = ("split_len", "waves_per_group", "unroll", "max_groups", "pack_cols", "lds_kib")
 
     def get_tune(self) -> dict:
         t = _native.Tune()
@@ -199,7 +203,7 @@ class Graph:
     def bfs(self, roots, semiring="selmax", *, slimwork: int = 2, split_len: int = -1,
             waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
             level_cap: int = 0, timing: bool = False, counters: bool = None,
-            want_parent: bool = True, want_real: bool = True,
+            persistent: bool = False, want_parent: bool = True, want_real: bool = True,
             dist=None, parent=None, real_val=None) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
@@ -228,14 +232,15 @@ class Graph:
         o.slimwork = int(slimwork)
         o.split_len = split_len
         o.waves_per_group = waves_per_group
-        o.schedule = schedule
+        o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         o.max_levels = max_levels
         o.stream = _stream_handle(stream)
         o.iterations_out = iters.ctypes.data_as(_native.c_i32p)
         if counters is None:
             counters = level_cap > 0
         o.flags = (_native.SS_STATS_TIME if timing else 0) | (
-            _native.SS_STATS_COUNTERS if counters else 0)
+            _native.SS_STATS_COUNTERS if counters else 0) | (
+            _native.SS_RUN_PERSISTENT if persistent else 0)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * (nr * level_cap))()
@@ -259,7 +264,8 @@ class Graph:
         return BfsResult(dist, parent, real_val, iters[:nr].copy(), levels, run_d)
 
     def bfs_batch(self, roots, *, slimwork: int = 2, max_levels: int = 0, stream=None,
-                  level_cap: int = 0, timing: bool = False, counters: bool = None, dist=None):
+                  level_cap: int = 0, timing: bool = False, counters: bool = None,
+                  persistent: bool = False, dist=None):
         """Batched BFS (64-bit frontier masks).  roots: int array [num_graphs, rpg]
         (graph-local IDs, -1 = unused slot) or [rpg] for a single graph.  Returns
         (dist tensor, iterations, levels, runs); dist holds each graph's block
@@ -283,7 +289,8 @@ class Graph:
         if counters is None:
             counters = level_cap > 0
         o.flags = (_native.SS_STATS_TIME if timing else 0) | (
-            _native.SS_STATS_COUNTERS if counters else 0)
+            _native.SS_STATS_COUNTERS if counters else 0) | (
+            _native.SS_RUN_PERSISTENT if persistent else 0)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * level_cap)()
@@ -320,6 +327,15 @@ class Graph:
         return dict(best={f: getattr(r.best, f) for f in self.TUNE_FIELDS}, best_ms=r.best_ms,
                     before_ms=r.before_ms, evaluated=r.evaluated, from_cache=bool(r.from_cache))
 
+    def sched_log(self, cap: int = 65536) -> np.ndarray:
+        """[levels, 12] record of the last scheduled run: features, scores,
+        variant, level."""
+        out = np.zeros((cap, 12), np.float32)
+        got = ctypes.c_int32()
+        check(_native.load().slimsell_sched_log(self._h, out.ctypes.data_as(_native.c_f32p), cap,
+                                                ctypes.byref(got)))
+        return out[:got.value]
+
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
             _native.load().slimsell_free(self._h)
@@ -334,3 +350,55 @@ class Graph:
 
 def sync(stream=None) -> None:
     check(_native.load().slimsell_sync(_stream_handle(stream)))
+
+
+# ------------------------------------------------------------ scheduler model
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _fp(a):
+    return a.ctypes.data_as(_native.c_f32p)
+
+
+def sched_load(weights) -> None:
+    """Install the process-wide scheduler model (1412 float32 parameters)."""
+    w = _f32(weights).reshape(-1)
+    check(_native.load().slimsell_sched_load(_fp(w), w.shape[0]))
+
+
+def sched_clear() -> None:
+    check(_native.load().slimsell_sched_clear())
+
+
+def sched_forward(weights, x) -> np.ndarray:
+    w, x = _f32(weights).reshape(-1), _f32(x).reshape(-1, _native.SCHED_FEATURES)
+    out = np.zeros((x.shape[0], _native.SCHED_VARIANTS), np.float32)
+    check(_native.load().slimsell_sched_forward(_fp(w), _fp(x), x.shape[0], _fp(out),
+                                                _stream_handle(None)))
+    return out
+
+
+def sched_grad(weights, x, y):
+    """(loss, gradient) of the MSE loss on the GPU."""
+    w = _f32(weights).reshape(-1)
+    x = _f32(x).reshape(-1, _native.SCHED_FEATURES)
+    y = _f32(y).reshape(-1, _native.SCHED_VARIANTS)
+    g = np.zeros(_native.SCHED_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    check(_native.load().slimsell_sched_grad(_fp(w), _fp(x), _fp(y), x.shape[0], _fp(g),
+                                             _fp(loss), _stream_handle(None)))
+    return float(loss[0]), g
+
+
+def sched_train(x, y, steps: int = 2000, lr: float = 3e-3, seed: int = 0, init=None):
+    """Train on the GPU; returns (weights, per-step loss)."""
+    x = _f32(x).reshape(-1, _native.SCHED_FEATURES)
+    y = _f32(y).reshape(-1, _native.SCHED_VARIANTS)
+    w = np.zeros(_native.SCHED_PARAMS, np.float32)
+    losses = np.zeros(max(steps, 1), np.float32)
+    ini = _fp(_f32(init).reshape(-1)) if init is not None else ctypes.cast(None, _native.c_f32p)
+    check(_native.load().slimsell_sched_train(_fp(x), _fp(y), x.shape[0], steps, lr, seed, ini,
+                                              _fp(w), _fp(losses), _stream_handle(None)))
+    return w, losses[:steps]

@@ -26,7 +26,10 @@ EXPORTS = [
     "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get", "slimsell_free",
     "slimsell_bfs", "slimsell_sync", "slimsell_last_error", "slimsell_version",
     "slimsell_build_multi", "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
+    "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log", "slimsell_sched_grad",
+    "slimsell_sched_forward", "slimsell_sched_train",
 ]
+SCHED_PARAMS, SCHED_FEATURES, SCHED_VARIANTS = 1412, 6, 4
 
 
 class LayoutView(ctypes.Structure):
@@ -41,9 +44,9 @@ class LayoutView(ctypes.Structure):
 
 class LevelStats(ctypes.Structure):
     _fields_ = [
-        ("discovered", ctypes.c_int64), ("active_chunks", ctypes.c_int64),
-        ("active_cells", ctypes.c_int64), ("max_active_cl", ctypes.c_int64),
-        ("ms", ctypes.c_float), ("pad0", ctypes.c_int32),
+        ("discovered", ctypes.c_int64), ("frontier_edges", ctypes.c_int64),
+        ("active_chunks", ctypes.c_int64), ("active_cells", ctypes.c_int64),
+        ("max_active_cl", ctypes.c_int64), ("ms", ctypes.c_float), ("variant", ctypes.c_int32),
     ]
 
 
@@ -58,7 +61,7 @@ class Tune(ctypes.Structure):
     _fields_ = [
         ("split_len", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
         ("unroll", ctypes.c_int32), ("max_groups", ctypes.c_int32),
-        ("pack_cols", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("pack_cols", ctypes.c_int32), ("lds_kib", ctypes.c_int32),
     ]
 
 
@@ -79,6 +82,7 @@ class AutotuneResult(ctypes.Structure):
 
 SS_STATS_TIME = 1
 SS_STATS_COUNTERS = 2
+SS_RUN_PERSISTENT = 4
 
 
 class BfsOpts(ctypes.Structure):
@@ -130,6 +134,15 @@ def load() -> ctypes.CDLL:
     lib.slimsell_bfs_batch.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.POINTER(BfsOpts), vp]
     lib.slimsell_autotune.argtypes = [vp, ctypes.POINTER(AutotuneOpts),
                                       ctypes.POINTER(AutotuneResult)]
+    lib.slimsell_sched_load.argtypes = [c_f32p, ctypes.c_int64]
+    lib.slimsell_sched_clear.argtypes = []
+    lib.slimsell_sched_log.argtypes = [vp, c_f32p, ctypes.c_int32, c_i32p]
+    lib.slimsell_sched_grad.argtypes = [c_f32p, c_f32p, c_f32p, ctypes.c_int64, c_f32p, c_f32p,
+                                        vp]
+    lib.slimsell_sched_forward.argtypes = [c_f32p, c_f32p, ctypes.c_int64, c_f32p, vp]
+    lib.slimsell_sched_train.argtypes = [c_f32p, c_f32p, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_float, ctypes.c_uint64, c_f32p, c_f32p, c_f32p,
+                                         vp]
     lib.slimsell_last_error.argtypes = []
     lib.slimsell_last_error.restype = ctypes.c_char_p
     lib.slimsell_version.argtypes = []
@@ -138,7 +151,9 @@ def load() -> ctypes.CDLL:
                  "slimsell_build_from_layout", "slimsell_graph_info",
                  "slimsell_graph_degrees", "slimsell_tune_set", "slimsell_tune_get",
                  "slimsell_bfs", "slimsell_sync", "slimsell_build_multi",
-                 "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune"):
+                 "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
+                 "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log",
+                 "slimsell_sched_grad", "slimsell_sched_forward", "slimsell_sched_train"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

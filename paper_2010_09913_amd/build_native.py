@@ -26,6 +26,7 @@ SOURCES = [
     ("kernels.hip", DEVICE_FLAGS),
     ("api.hip", DEVICE_FLAGS),
     ("autotune.hip", DEVICE_FLAGS),
+    ("sched.hip", DEVICE_FLAGS),
 ]
 
 

@@ -26,6 +26,19 @@ int set_error(int code, const std::string& msg) {
   return code;
 }
 
+static std::mutex g_model_mu;
+static std::vector<float> g_model;
+static uint64_t g_model_version = 0;  // 0 = no model
+static uint64_t g_model_counter = 0;
+
+bool sched_model(std::vector<float>* out, uint64_t* version) {
+  std::lock_guard<std::mutex> lk(g_model_mu);
+  if (g_model_version == 0) return false;
+  *out = g_model;
+  *version = g_model_version;
+  return true;
+}
+
 static int hip_fail(hipError_t e, const char* what) {
   return set_error(SS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -65,7 +78,10 @@ static void release_graph(Graph* g) {
                   g->ws.vec_a,  g->ws.vec_b, g->ws.state, g->ws.g, g->ws.d,
                   g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters,
                   g->d_voff,    g->bw.vis, g->bw.fa,   g->bw.fb,   g->bw.acc64,
-                  g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots};
+                  g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots,
+                  g->ws.q[0],   g->ws.q[1], g->ws.qn,   g->ws.variant, g->ws.ring_ctr,
+                  g->ws.sched_sums, g->ws.model, g->ws.sched_log, g->ws.bar, g->ws.pstatus,
+                  g->ws.segs,   g->ws.seg_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* ev : g->ev_pool)
@@ -179,6 +195,23 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.acc, g.n_pad))) return rc;
   if ((rc = dalloc(&ws.arrive, g.n_chunks))) return rc;
   SS_HIP(hipMemset(ws.arrive, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.n_chunks)));
+  if ((rc = dalloc(&ws.q[0], g.n_pad))) return rc;
+  if ((rc = dalloc(&ws.q[1], g.n_pad))) return rc;
+  if ((rc = dalloc(&ws.qn, kRing))) return rc;
+  if ((rc = dalloc(&ws.variant, kRing))) return rc;
+  if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kCountSlots * kCountFields))) return rc;
+  if ((rc = dalloc(&ws.sched_sums, 4))) return rc;
+  if ((rc = dalloc(&ws.model, kModelSize))) return rc;
+  ws.sched_log_cap = std::min<int64_t>((int64_t)g.n + 2, 65536);
+  if ((rc = dalloc(&ws.sched_log, ws.sched_log_cap * 12))) return rc;
+  // segments of long frontier rows: at most one per frontier row plus one per
+  // 1024 cells of the graph
+  ws.seg_cap = (int64_t)g.n_pad + g.entries / 1024 + 64;
+  if ((rc = dalloc(&ws.segs, ws.seg_cap))) return rc;
+  if ((rc = dalloc(&ws.seg_n, 2))) return rc;
+  SS_HIP(hipMemset(ws.seg_n, 0, sizeof(int32_t) * 2));
+  if ((rc = dalloc(&ws.bar, 2))) return rc;
+  if ((rc = dalloc(&ws.pstatus, 4))) return rc;
   if ((rc = dalloc(&ws.any, kRing))) return rc;
   SS_HIP(hipMemset(ws.any, 0, sizeof(uint64_t) * kRing));
   void* h = nullptr;
@@ -239,9 +272,13 @@ uint32_t next_run_id(Graph& g) {
 struct RunPlan {
   int waves = 4, unroll = 8;
   int64_t max_groups = 0, cap = 0, lcap = 0, words_per_run = 0;
-  bool timing = false, counting = false;
+  bool timing = false, counting = false, persistent = false;
   int32_t slimwork = 2;
+  int32_t schedule = 0;
+  uint32_t lds_bytes = 0;
   UnitList* ul = nullptr;
+  UnitList* vul[kPullVariants] = {nullptr, nullptr, nullptr};  // pull variants
+  bool has_model = false;
 };
 
 // Per-call record of what was launched, for the statistics epilogue.
@@ -253,8 +290,8 @@ struct RunLog {
   std::vector<int32_t> iters;
 };
 
-static int plan_run(Graph& g, const ss_bfs_opts* o, int32_t runs, int64_t default_cap,
-                    hipStream_t st, RunPlan* p) {
+static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
+                    int64_t default_cap, hipStream_t st, RunPlan* p) {
   if (o->size != sizeof(ss_bfs_opts)) return set_error(SS_EINVAL, "opts->size mismatch");
   if (o->slimwork < 0 || o->slimwork > 2) return set_error(SS_EINVAL, "slimwork must be 0, 1 or 2");
   p->waves = o->waves_per_group ? o->waves_per_group : g.tune.waves_per_group;
@@ -268,10 +305,38 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int32_t runs, int64_t defaul
   p->max_groups = g.tune.max_groups;
   p->cap = (o->max_levels > 0) ? std::min<int64_t>(o->max_levels, default_cap) : default_cap;
   if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
-  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS)) return set_error(SS_EINVAL, "bad flags");
+  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT))
+    return set_error(SS_EINVAL, "bad flags");
+  p->persistent = (o->flags & SS_RUN_PERSISTENT) != 0;
+  if (p->persistent && o->schedule) return set_error(SS_EINVAL, "persistent runs need schedule = 0");
   p->slimwork = o->slimwork;
+  p->lds_bytes = 0;
+  if (g.tune.lds_kib > 0) {
+    // bytes of the gathered vector each policy reads, rounded down to 16
+    const int64_t used = policy == SS_BOOLEAN     ? g.n_pad
+                         : policy == SS_SELMAX    ? g.n_pad / 8
+                         : policy == kBatchSemiring ? g.n_pad * 8
+                                                  : g.n_pad * 4;
+    p->lds_bytes = (uint32_t)(std::min<int64_t>(used, (int64_t)g.tune.lds_kib * 1024) / 16 * 16);
+  }
+  if (o->schedule < 0 || o->schedule > 3 + kVariants - 1)
+    return set_error(SS_EINVAL, "schedule must be 0..6");
+  if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
+  p->schedule = o->schedule;
   int rc = get_units(g, split, pack, &p->ul);
   if (rc) return rc;
+  if (p->schedule) {
+    const int32_t vsplit[kPullVariants] = {0, 256, 1024};
+    for (int v = 0; v < kPullVariants; ++v)
+      if ((rc = get_units(g, vsplit[v], 0, &p->vul[v]))) return rc;
+    std::vector<float> host;
+    uint64_t version = 0;
+    p->has_model = (p->schedule == 1) && sched_model(&host, &version);
+    if (p->has_model && g.ws.model_version != version) {
+      SS_HIP(hipMemcpy(g.ws.model, host.data(), sizeof(float) * kModelSize, hipMemcpyHostToDevice));
+      g.ws.model_version = version;
+    }
+  }
   p->timing = (o->flags & SS_STATS_TIME) != 0;
   p->lcap = o->level_cap;
   p->counting = (o->flags & SS_STATS_COUNTERS) && p->lcap > 0 && o->level_stats_out;
@@ -320,6 +385,18 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
   a.run_id = run;
   a.n_pad = (uint32_t)g.n_pad;
   a.slimwork = p.slimwork;
+  a.lds_bytes = p.lds_bytes;
+  if (p.schedule) {
+    a.variant = g.ws.variant;
+    for (int v = 0; v < kPullVariants; ++v) {
+      a.vunits[v] = p.vul[v]->d_units;
+      a.vpieces[v] = p.vul[v]->d_pieces;
+      a.vn_units[v] = p.vul[v]->count;
+    }
+    a.qn = g.ws.qn;
+    a.want_queue = 1;
+    a.ring_ctr = g.ws.ring_ctr;
+  }
   (void)o;
   return a;
 }
@@ -327,14 +404,72 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
 // The level loop of one BFS run: level kernels are enqueued kLookahead ahead
 // of the level being waited on; the run ends at the first level that
 // discovers nothing.
+static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, void* buf_a,
+                          void* buf_b, hipStream_t st, RunLog* log, int32_t run_idx) {
+  int rc;
+  if ((rc = launch_fill_i32(reinterpret_cast<int32_t*>(g.ws.bar), 0, 2, st))) return rc;
+  if ((rc = launch_fill_i32(g.ws.pstatus, 0, 4, st))) return rc;
+  const int32_t lcap = (int32_t)std::min<int64_t>(p.lcap, INT32_MAX);
+  if ((rc = launch_fill_i32(g.ws.pstatus + 2, lcap, 1, st))) return rc;
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g.device) != hipSuccess ||
+      rate_khz <= 0)
+    rate_khz = 100000;
+  const uint64_t limit = (uint64_t)rate_khz * 1000ull * 5ull;  // 5 s per barrier wait
+  a.count_stats = p.counting ? 1 : 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p.timing) {
+    if ((rc = pool_event(g, log->next_ev++, &e0))) return rc;
+    if ((rc = pool_event(g, log->next_ev++, &e1))) return rc;
+    SS_HIP(hipEventRecord(e0, st));
+  }
+  rc = launch_persistent(policy, p.waves, p.unroll, p.max_groups, a, buf_a, buf_b,
+                         (int32_t)std::min<int64_t>(p.cap, INT32_MAX), g.ws.bar, g.ws.pstatus,
+                         limit, st);
+  if (rc) return rc;
+  if (p.timing) SS_HIP(hipEventRecord(e1, st));
+  int32_t status[4] = {0, 0, 0, 0};
+  SS_HIP(hipMemcpyAsync(status, g.ws.pstatus, sizeof(status), hipMemcpyDeviceToHost, st));
+  SS_HIP(hipStreamSynchronize(st));
+  if (status[1]) return set_error(SS_EHIP, "persistent kernel: a level barrier timed out");
+  if (status[0] < 0) return set_error(SS_EITER, "level cap reached before the BFS finished");
+  log->iters[run_idx] = status[0];
+  log->launches[run_idx] = 1;
+  return SS_OK;
+}
+
 static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void* buf_a,
                       void* buf_b, hipStream_t st, RunLog* log, int32_t run_idx) {
+  if (p.persistent) return run_persistent(g, p, policy, a, buf_a, buf_b, st, log, run_idx);
   constexpr int kLookahead = 2;
   int32_t launched = 0;
+  SchedLaunch sl;
+  std::memset(&sl, 0, sizeof(sl));
+  if (p.schedule) {
+    sl.any = g.ws.any;
+    sl.report = g.ws.d_report;
+    sl.variant = g.ws.variant;
+    sl.qn = g.ws.qn;
+    sl.seg_n = g.ws.seg_n;
+    sl.ring_ctr = g.ws.ring_ctr;
+    sl.sums = g.ws.sched_sums;
+    sl.model = p.has_model ? g.ws.model : nullptr;
+    sl.log = g.ws.sched_log;
+    sl.log_cap = (int32_t)g.ws.sched_log_cap;
+    sl.mode = p.schedule;
+    sl.heuristic_pull = g.tune.split_len == 0 ? 0 : (g.tune.split_len <= 512 ? 1 : 2);
+    sl.n = (double)g.n;
+    sl.two_m = (double)g.entries;
+    sl.mean_degree = g.n ? (double)g.entries / (double)g.n : 0.0;
+  }
   auto launch = [&](int32_t k) -> int {
     a.level = k;
     a.vin = (k & 1) ? buf_a : buf_b;
     a.vout = (k & 1) ? buf_b : buf_a;
+    a.q_in = g.ws.q[(k - 1) & 1];
+    a.q_out = g.ws.q[k & 1];
+    a.segs = g.ws.segs;
+    a.seg_n = g.ws.seg_n + (k & 1);
     a.count_stats = (p.counting && k <= p.lcap) ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p.timing) {
@@ -343,8 +478,18 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
       if ((pr = pool_event(g, log->next_ev++, &e1))) return pr;
       SS_HIP(hipEventRecord(e0, st));
     }
-    int lr = launch_level(policy, p.waves, p.unroll, p.max_groups, a, st);
-    if (lr) return lr;
+    int lr;
+    if (p.schedule) {
+      if ((lr = launch_schedule(sl, k, a.run_id, st))) return lr;
+      LevelArgs pa = a;
+      int64_t most = 0;
+      for (int v = 0; v < kPullVariants; ++v) most = std::max(most, pa.vn_units[v]);
+      pa.n_units = most;  // grid size only: the kernel uses its variant's units
+      if ((lr = launch_level(policy, p.waves, p.unroll, p.max_groups, pa, st))) return lr;
+      if ((lr = launch_push(policy, a, st))) return lr;
+    } else {
+      if ((lr = launch_level(policy, p.waves, p.unroll, p.max_groups, a, st))) return lr;
+    }
     if (p.timing) SS_HIP(hipEventRecord(e1, st));
     return SS_OK;
   };
@@ -382,6 +527,14 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
                      hipMemcpyDeviceToHost));
   }
   auto ev = [&](size_t i) { return static_cast<hipEvent_t>(g.ev_pool[i]); };
+  std::vector<float> hlog;  // schedule log of the last run (variants per level)
+  if (p.schedule && want_levels && runs == 1) {
+    const int64_t nl = std::min<int64_t>(std::min<int64_t>(p.lcap, log.iters[0]), g.ws.sched_log_cap);
+    hlog.resize((size_t)nl * 12);
+    if (nl > 0)
+      SS_HIP(hipMemcpy(hlog.data(), g.ws.sched_log, sizeof(float) * hlog.size(),
+                       hipMemcpyDeviceToHost));
+  }
   for (int32_t r = 0; r < runs; ++r) {
     float kernel_ms = 0.f, bfs_ms = 0.f;
     std::vector<float> lvl_ms((size_t)log.launches[r], 0.f);
@@ -394,6 +547,7 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
         kernel_ms += ms;
       }
       SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1 + 2 * log.launches[r])));
+      if (p.persistent) std::fill(lvl_ms.begin(), lvl_ms.end(), 0.f);  // one launch, all levels
     }
     if (o->run_stats_out) {
       ss_run_stats& rs = o->run_stats_out[r];
@@ -407,7 +561,9 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
         ss_level_stats& ls = o->level_stats_out[r * p.lcap + (k - 1)];
         std::memset(&ls, 0, sizeof(ls));
         if (k > log.iters[r]) continue;
-        ls.ms = p.timing ? lvl_ms[k - 1] : 0.f;
+        ls.ms = (p.timing && k - 1 < (int64_t)lvl_ms.size()) ? lvl_ms[k - 1] : 0.f;
+        ls.variant = -1;
+        if (p.schedule && k <= (int64_t)hlog.size() / 12) ls.variant = (int32_t)hlog[(k - 1) * 12 + 10];
         if (p.counting) {
           const unsigned long long* base = h.data() + p.words_per_run * r;
           for (int q = 0; q < kCountSlots; ++q) {
@@ -416,6 +572,7 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
             ls.active_chunks += (int64_t)f[1];
             ls.active_cells += (int64_t)f[2];
             ls.max_active_cl = std::max<int64_t>(ls.max_active_cl, (int64_t)f[3]);
+            ls.frontier_edges += (int64_t)f[4];
           }
         }
       }
@@ -467,6 +624,22 @@ extern "C" {
 const char* slimsell_last_error(void) { return g_last_error.c_str(); }
 
 const char* slimsell_version(void) { return "slimsell-mi355x 0.1 (gfx950)"; }
+
+int slimsell_sched_load(const float* w, int64_t count) {
+  if (!w || count != kModelSize)
+    return set_error(SS_EINVAL, "the scheduler model has exactly 1412 parameters");
+  std::lock_guard<std::mutex> lk(g_model_mu);
+  g_model.assign(w, w + kModelSize);
+  g_model_version = ++g_model_counter;
+  return SS_OK;
+}
+
+int slimsell_sched_clear(void) {
+  std::lock_guard<std::mutex> lk(g_model_mu);
+  g_model.clear();
+  g_model_version = 0;
+  return SS_OK;
+}
 
 int slimsell_layout_build(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t C,
                           int32_t sigma, ss_layout** out) {
@@ -601,9 +774,10 @@ int slimsell_tune_set(ss_graph* g, const ss_tune* t) {
     return set_error(SS_EINVAL, "unroll must be 4, 8 or 16");
   if (t->max_groups < 0) return set_error(SS_EINVAL, "max_groups must be >= 0");
   if (t->pack_cols < -1) return set_error(SS_EINVAL, "pack_cols must be >= -1");
+  if (t->lds_kib != 0 && t->lds_kib != 16 && t->lds_kib != 32 && t->lds_kib != 64)
+    return set_error(SS_EINVAL, "lds_kib must be 0, 16, 32 or 64");
   std::lock_guard<std::mutex> lock(g->mu);
   g->tune = *t;
-  g->tune.pad0 = 0;
   return SS_OK;
 }
 
@@ -645,7 +819,7 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   SS_HIP(hipSetDevice(g.device));
   hipStream_t st = static_cast<hipStream_t>(o->stream);
   RunPlan plan;
-  int rc = plan_run(g, o, num_roots, (int64_t)g.n + 1, st, &plan);
+  int rc = plan_run(g, o, (int)s, num_roots, (int64_t)g.n + 1, st, &plan);
   if (rc) return rc;
   RunLog log((size_t)num_roots);
   for (int32_t r = 0; r < num_roots; ++r) {
@@ -653,6 +827,7 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[r]))) return rc;
     rc = launch_init(s, g, g.ws, g.h_perm[roots[r]], st);
     if (rc) return rc;
+    if (plan.schedule && (rc = launch_sched_init(g, g.ws, g.h_perm[roots[r]], st))) return rc;
     LevelArgs a = base_args(g, plan, o, run, r);
     rc = run_levels(g, plan, (int)s, a, g.ws.vec_a, g.ws.vec_b, st, &log, r);
     if (rc) return rc;
@@ -691,7 +866,9 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
   SS_HIP(hipSetDevice(g.device));
   hipStream_t st = static_cast<hipStream_t>(o->stream);
   RunPlan plan;
-  int rc = plan_run(g, o, 1, std::min<int64_t>((int64_t)g.n + 1, 65534), st, &plan);
+  if (o->schedule) return set_error(SS_EINVAL, "batched BFS has no per-level schedule");
+  int rc = plan_run(g, o, kBatchSemiring, 1, std::min<int64_t>((int64_t)g.n + 1, 65534), st,
+                    &plan);
   if (rc) return rc;
   if ((rc = ensure_batch_workspace(g, (int64_t)root_rows.size(), full, st))) return rc;
   BatchWorkspace& bw = g.bw;
@@ -718,6 +895,15 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
   if (rc) return rc;
   if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
   return collect_stats(g, o, plan, 1, log, st);
+}
+
+int slimsell_sched_log(const ss_graph* g, float* out, int32_t cap, int32_t* levels) {
+  if (!g || !out || cap < 0) return set_error(SS_EINVAL, "bad argument");
+  const int64_t nl = std::min<int64_t>(cap, g->ws.sched_log_cap);
+  if (nl > 0)
+    SS_HIP(hipMemcpy(out, g->ws.sched_log, sizeof(float) * (size_t)nl * 12, hipMemcpyDeviceToHost));
+  if (levels) *levels = (int32_t)nl;
+  return SS_OK;
 }
 
 int slimsell_graph_parts(const ss_graph* g, int32_t* num_graphs, int64_t* n_per_graph,

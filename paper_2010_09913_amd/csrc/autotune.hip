@@ -113,17 +113,23 @@ extern "C" int slimsell_autotune(ss_graph* gp, const ss_autotune_opts* o, ss_aut
   const std::vector<int32_t> unrolls = {4, 8, 16};
   const std::vector<int32_t> groups = {0, 1024, 4096};
   const std::vector<int32_t> packs = {0, 32, 128};
+  const std::vector<int32_t> stages = {0, 32, 64};
   for (int pass = 0; pass < 2 && rc == SS_OK; ++pass) {
-    for (int dim = 0; dim < 5 && rc == SS_OK; ++dim) {
-      const std::vector<int32_t>& vals =
-          dim == 0 ? splits : dim == 1 ? waves : dim == 2 ? unrolls : dim == 3 ? groups : packs;
+    for (int dim = 0; dim < 6 && rc == SS_OK; ++dim) {
+      const std::vector<int32_t>& vals = dim == 0   ? splits
+                                         : dim == 1 ? waves
+                                         : dim == 2 ? unrolls
+                                         : dim == 3 ? groups
+                                         : dim == 4 ? packs
+                                                    : stages;
       for (int32_t v : vals) {
         ss_tune t = best;
         int32_t* field = dim == 0   ? &t.split_len
                          : dim == 1 ? &t.waves_per_group
                          : dim == 2 ? &t.unroll
                          : dim == 3 ? &t.max_groups
-                                    : &t.pack_cols;
+                         : dim == 4 ? &t.pack_cols
+                                    : &t.lds_kib;
         if (*field == v) continue;
         *field = v;
         float ms = 0.f;

@@ -1,6 +1,8 @@
 // Internal declarations of libslimsell (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -15,6 +17,9 @@ constexpr int kC = SS_CHUNK_HEIGHT;  // rows per chunk = wavefront width on CDNA
 constexpr int32_t kInf = 0x7FFFFFFE; // tropical infinity; kInf + 1 does not overflow
 
 int set_error(int code, const std::string& msg);
+
+// Process-wide scheduler model (slimsell_sched_load); version 0 = none.
+bool sched_model(std::vector<float>* out, uint64_t* version);
 
 // Host layout (arrays described in slimsell.h, ss_layout_view).
 struct Layout {
@@ -64,6 +69,21 @@ struct Workspace {
   uint64_t* any = nullptr;    // [kRing] per-level tag (run_id << 32 | level) if it found rows
   unsigned long long* counters = nullptr;  // per-level counters, see LevelArgs::counters
   int64_t counter_words = 0;               // capacity of counters[]
+  // frontier queues (rows discovered at a level), learned-schedule state
+  int32_t* q[2] = {nullptr, nullptr};  // [n_pad] each, by level parity
+  int32_t* qn = nullptr;               // [kRing] queue length per level
+  int32_t* variant = nullptr;          // [kRing] chosen variant per level
+  unsigned long long* ring_ctr = nullptr;  // [kRing * kCountSlots * kCountFields]
+  double* sched_sums = nullptr;        // [4] running totals for the features
+  float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
+  int64_t sched_log_cap = 0;
+  float* model = nullptr;              // [kModelSize] device copy of the scheduler model
+  uint64_t model_version = 0;          // version of the process model copied there
+  int2* segs = nullptr;                 // push segments: capacity seg_cap
+  int64_t seg_cap = 0;
+  int32_t* seg_n = nullptr;             // [2] segment counts by level parity
+  unsigned* bar = nullptr;              // [2] grid barrier of the persistent kernel
+  int32_t* pstatus = nullptr;           // [4] persistent run: levels, error, level cap
   // host-mapped report ring written by the GPU: (tag << 1) | found
   volatile uint64_t* h_report = nullptr;
   uint64_t* d_report = nullptr;  // device view of h_report
@@ -86,7 +106,15 @@ struct BatchWorkspace {
 };
 
 constexpr int kCountSlots = 16;  // counter atomics are spread over this many slots
-constexpr int kCountFields = 4;  // discovered, active chunks, active columns, max active cl
+// counter fields: discovered, active chunks, active cells, max active cl,
+// degree sum of the discovered rows (frontier edges of the next level)
+constexpr int kCountFields = 5;
+constexpr int kVariants = 4;     // learned-schedule variants
+constexpr int kPullVariants = 3; // pull with split 0 / 256 / 1024; variant 3 = push
+constexpr int kPush = 3;
+constexpr int kStop = -2;        // variant tag of a level past the end of the BFS
+constexpr int kModelSize = 6 * 32 + 32 + 32 * 32 + 32 + 32 * 4 + 4;  // 1412 parameters
+constexpr int kFeatures = 6;
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
 
 struct Graph {
@@ -113,7 +141,8 @@ struct Graph {
   std::vector<int64_t> h_roff;    // [num_graphs + 1] row offset of each graph
   int64_t* d_voff = nullptr;
   uint32_t run_id = 0;
-  ss_tune tune{256, 1, 8, 0, 0, 0};  // launch configuration (slimsell_tune_set / autotune)
+  ss_tune tune{256, 16, 8, 512, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
+  int32_t lds_cap = 0;                // largest LDS prefix the device allows, bytes
   std::mutex mu;
 };
 
@@ -139,6 +168,18 @@ struct LevelArgs {
   // per-level counters of this root: [(level * kCountSlots + slot) * kCountFields + field]
   unsigned long long* counters;
   uint64_t* report;
+  // learned schedule / push variant (variant == nullptr: pull with `units`)
+  const int32_t* variant;
+  const Unit* vunits[kPullVariants];
+  const int32_t* vpieces[kPullVariants];
+  int64_t vn_units[kPullVariants];
+  const int32_t* q_in;   // frontier rows of the previous level
+  int32_t* q_out;        // frontier rows of this level
+  int32_t* qn;           // [kRing] queue lengths
+  int32_t want_queue;
+  unsigned long long* ring_ctr;  // per-level counters for the schedule (ring)
+  int2* segs;            // push: segments (row, first cell) of long frontier rows
+  int32_t* seg_n;        // push: segment count of this level (cleared by the schedule kernel)
   // batched SpMM only
   unsigned long long* acc64;
   unsigned long long* vis;
@@ -146,12 +187,36 @@ struct LevelArgs {
   uint16_t* lvl;
   uint32_t run_id;
   uint32_t n_pad;    // rows (multiple of 64)
+  uint32_t lds_bytes;  // prefix of the gathered vector staged in LDS (0 = none)
   int32_t level;     // k >= 1
   int32_t slimwork;
   int32_t count_stats;
 };
 
+// Parameters of the schedule kernel that stay fixed over one run.
+struct SchedLaunch {
+  uint64_t* any;
+  uint64_t* report;
+  int32_t* variant;
+  int32_t* qn;
+  int32_t* seg_n;
+  unsigned long long* ring_ctr;
+  double* sums;
+  const float* model;
+  float* log;
+  int32_t log_cap;
+  int32_t mode;
+  int32_t heuristic_pull;
+  double n, two_m, mean_degree;
+};
+
 // Kernel launchers (kernels.hip).
+int launch_push(int semiring, const LevelArgs& a, void* stream);
+int launch_persistent(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
+                      void* buf_a, void* buf_b, int32_t cap, unsigned* bar, int32_t* status,
+                      uint64_t deadline, void* stream);
+int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream);
+int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
                  void* stream);

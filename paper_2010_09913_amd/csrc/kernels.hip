@@ -54,6 +54,46 @@ __device__ __forceinline__ uint32_t off_of(int32_t c, int shift) {
   return c >= 0 ? ((uint32_t)c << shift) : kOob;
 }
 
+// LDS-staged prefix of the gathered vector.  With a full sort the rows of
+// highest degree (the most gathered) come first, so each workgroup copies the
+// first `bytes` of the vector into LDS once per level; a gather whose byte
+// offset falls inside reads LDS, any other reads global memory.  The two
+// loads are issued branch-free: the LDS read uses a clamped address and is
+// masked, the buffer load gets an out-of-range offset when LDS serves it.
+struct Stage {
+  const uint8_t* lds;
+  uint32_t bytes;  // 0 = nothing staged
+};
+
+template <bool STAGED>
+__device__ __forceinline__ uint32_t gather_b32(Rsrc r, Stage st, uint32_t off) {
+  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  const bool in = off < st.bytes;
+  uint32_t l = *reinterpret_cast<const uint32_t*>(st.lds + (in ? off : 0u));
+  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b32(r, in ? kOob : off, 0, 0);
+  return (in ? l : 0u) | g;
+}
+template <bool STAGED>
+__device__ __forceinline__ uint32_t gather_b8(Rsrc r, Stage st, uint32_t off) {
+  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+  const bool in = off < st.bytes;
+  const uint32_t l = st.lds[in ? off : 0u];
+  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b8(r, in ? kOob : off, 0, 0);
+  return (in ? l : 0u) | g;
+}
+template <bool STAGED>
+__device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint32_t off) {
+  unsigned long long l = 0ull;
+  bool in = false;
+  if (STAGED) {
+    in = off < st.bytes;
+    l = *reinterpret_cast<const unsigned long long*>(st.lds + (in ? off : 0u));
+  }
+  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, in ? kOob : off, 0, 0);
+  const unsigned long long g = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
+  return (in ? l : 0ull) | g;
+}
+
 // Returning atomics, so that the wait that follows covers their completion.
 __device__ __forceinline__ void keep(int32_t v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -66,11 +106,13 @@ struct Tropical {
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
   // terms 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
-  template <int U>
-  __device__ static Acc block(const LevelArgs& a, Rsrc r, const int32_t (&c)[U], Acc acc) {
+  __device__ static const void* staged(const LevelArgs& a) { return a.state; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc) {
     int32_t y[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = __builtin_amdgcn_raw_buffer_load_b32(r, off_of(c[t], 2), 0, 0);
+    for (int t = 0; t < U; ++t) y[t] = (int32_t)gather_b32<STAGED>(r, st, off_of(c[t], 2));
 #pragma unroll
     for (int t = 0; t < U; ++t) {
       const int32_t term = (c[t] >= 0 && y[t] < a.level) ? y[t] + 1 : kInf;
@@ -82,6 +124,12 @@ struct Tropical {
     keep(atomicMin(&a.acc[row], v));
   }
   __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc[row], kInf); }
+  // push: a frontier row u (distance k-1) offers k to its neighbours
+  __device__ static Acc push_value(const LevelArgs& a, int32_t) { return a.level; }
+  __device__ static bool claim(const LevelArgs& a, int32_t w, Acc v) {
+    return atomicMin(&a.acc[w], v) == kInf;
+  }
+  __device__ static void publish_one(const LevelArgs&, int32_t) {}
   // f_k^row = min(f_{k-1}^row, acc): the zero diagonal of A' keeps the old value
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const int32_t own = a.state[row];
@@ -100,12 +148,14 @@ struct Real {
   __device__ static Acc identity() { return 0.0f; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
-  template <int U>
-  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+  __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc) {
     float y[U];
 #pragma unroll
     for (int t = 0; t < U; ++t)
-      y[t] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off_of(c[t], 2), 0, 0));
+      y[t] = __int_as_float((int32_t)gather_b32<STAGED>(r, st, off_of(c[t], 2)));
 #pragma unroll
     for (int t = 0; t < U; ++t) acc += y[t];
     return acc;
@@ -116,6 +166,11 @@ struct Real {
   __device__ static Acc take(const LevelArgs& a, int32_t row) {
     return atomicExch(reinterpret_cast<float*>(&a.acc[row]), 0.0f);
   }
+  __device__ static Acc push_value(const LevelArgs&, int32_t) { return 1.0f; }
+  __device__ static bool claim(const LevelArgs& a, int32_t w, Acc v) {
+    return atomicAdd(reinterpret_cast<float*>(&a.acc[w]), v) == 0.0f;
+  }
+  __device__ static void publish_one(const LevelArgs&, int32_t) {}
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const uint8_t gg = a.g[row];
     const bool fresh = (acc * (float)gg) != 0.0f;
@@ -136,11 +191,13 @@ struct Boolean {
   __device__ static Acc identity() { return 0u; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
-  template <int U>
-  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+  __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc) {
     uint32_t y[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = __builtin_amdgcn_raw_buffer_load_b8(r, off_of(c[t], 0), 0, 0);
+    for (int t = 0; t < U; ++t) y[t] = gather_b8<STAGED>(r, st, off_of(c[t], 0));
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -151,6 +208,11 @@ struct Boolean {
   __device__ static Acc take(const LevelArgs& a, int32_t row) {
     return atomicExch(reinterpret_cast<uint32_t*>(&a.acc[row]), 0u);
   }
+  __device__ static Acc push_value(const LevelArgs&, int32_t) { return 1u; }
+  __device__ static bool claim(const LevelArgs& a, int32_t w, Acc v) {
+    return atomicOr(reinterpret_cast<uint32_t*>(&a.acc[w]), v) == 0u;
+  }
+  __device__ static void publish_one(const LevelArgs&, int32_t) {}
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (acc != 0u) && (a.g[row] != 0);
     static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
@@ -178,14 +240,15 @@ struct SelMax {
     return make_rsrc(a.vin, (uint32_t)(a.n_pad / kC) * 8u);
   }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
-  template <int U>
-  __device__ static Acc block(const LevelArgs& a, Rsrc r, const int32_t (&c)[U], Acc acc) {
+  __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc) {
     const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
     uint32_t w[U];
 #pragma unroll
     for (int t = 0; t < U; ++t)  // the 32-bit half of the chunk word holding bit c
-      w[t] = __builtin_amdgcn_raw_buffer_load_b32(r, c[t] >= 0 ? ((uint32_t)c[t] >> 5) << 2 : kOob,
-                                                  0, 0);
+      w[t] = gather_b32<STAGED>(r, st, c[t] >= 0 ? ((uint32_t)c[t] >> 5) << 2 : kOob);
     int32_t x[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
@@ -200,6 +263,14 @@ struct SelMax {
     keep(atomicMax(&a.acc[row], v));
   }
   __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc[row], 0); }
+  __device__ static Acc push_value(const LevelArgs& a, int32_t u) { return a.v[u]; }
+  __device__ static bool claim(const LevelArgs& a, int32_t w, Acc v) {
+    return atomicMax(&a.acc[w], v) == 0;
+  }
+  // a row entering the frontier in a push level sets its bit in the word
+  __device__ static void publish_one(const LevelArgs& a, int32_t row) {
+    atomicOr(static_cast<unsigned long long*>(a.vout) + (row >> 6), 1ull << (row & 63));
+  }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (a.state[row] == 0) && (acc != 0);
     if (fresh) {
@@ -226,14 +297,13 @@ struct Batch {
     const Acc full = a.full[row / kC];
     return (a.vis[row] & full) != full;
   }
-  template <int U>
-  __device__ static Acc block(const LevelArgs&, Rsrc r, const int32_t (&c)[U], Acc acc) {
+  __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc) {
     Acc y[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) {
-      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off_of(c[t], 3), 0, 0);
-      y[t] = ((Acc)w[1] << 32) | (Acc)w[0];
-    }
+    for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, off_of(c[t], 3));
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -271,8 +341,8 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 // Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
 // U independent streaming loads of `col`, then the U gathers of the block.  A
 // lane that is off (its row is final) issues no loads at all.
-template <class S, int U>
-__device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r,
+template <class S, int U, bool STAGED>
+__device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Stage st,
                                                  const int32_t* __restrict__ p, int32_t ncols,
                                                  bool on) {
   typename S::Acc acc = S::identity();
@@ -282,58 +352,106 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r,
     int32_t c[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
-    acc = S::template block<U>(a, r, c, acc);
+    acc = S::template block<U, STAGED>(a, r, st, c, acc);
     p += (int64_t)U * kC;
   }
   for (; j < ncols; ++j) {
     int32_t c[1] = {__builtin_nontemporal_load(p)};
-    acc = S::template block<1>(a, r, c, acc);
+    acc = S::template block<1, STAGED>(a, r, st, c, acc);
     p += kC;
   }
   return acc;
 }
 
-// Post-process the rows of one chunk; returns how many entered the frontier.
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
+// Append this lane's row to the level's frontier queue when `fresh`; one
+// atomic per wavefront.
+__device__ __forceinline__ void queue_append(const LevelArgs& a, bool fresh, int32_t row,
+                                             int lane) {
+  const uint64_t m = __ballot(fresh);
+  if (!m) return;
+  const int leader = __ffsll((long long)m) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(&a.qn[a.level % kRing], (int32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (fresh) a.q_out[base + __popcll(m & lanes_below(lane))] = row;
+}
+
+// Post-process the rows of one chunk; returns how many entered the frontier
+// and adds their degrees to `fdeg`.
 template <class S>
 __device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chunk, int32_t row,
-                                                typename S::Acc acc, int lane) {
+                                                typename S::Acc acc, int lane, uint64_t& fdeg) {
   const bool fresh = S::post(a, row, acc);
   const uint64_t mask = __ballot(fresh);
   S::publish(a, chunk, mask, lane);
+  if (fresh) fdeg += (uint64_t)a.deg[row];
+  if (a.want_queue) queue_append(a, fresh, row, lane);
   return (uint32_t)__popcll(mask);
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Flush one wavefront's tallies into the statistics and schedule counters.
+__device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uint32_t found,
+                                               uint32_t n_chunks, uint64_t n_cells,
+                                               int32_t max_cl, uint64_t fdeg_lane) {
+  const uint64_t fdeg = wave_sum64(fdeg_lane);
+  if (lane != 0 || !(found | n_chunks | n_cells | fdeg)) return;
+  unsigned long long* dst[2] = {nullptr, nullptr};
+  const int slot = blockIdx.x % kCountSlots;
+  if (a.count_stats)
+    dst[0] = a.counters + ((int64_t)a.level * kCountSlots + slot) * kCountFields;
+  if (a.ring_ctr)
+    dst[1] = a.ring_ctr + ((int64_t)(a.level % kRing) * kCountSlots + slot) * kCountFields;
+  for (unsigned long long* ctr : dst) {
+    if (!ctr) continue;
+    if (found) atomicAdd(&ctr[0], (unsigned long long)found);
+    if (n_chunks) {
+      atomicAdd(&ctr[1], (unsigned long long)n_chunks);
+      atomicMax(&ctr[3], (unsigned long long)max_cl);
+    }
+    if (n_cells) atomicAdd(&ctr[2], (unsigned long long)n_cells);
+    if (fdeg) atomicAdd(&ctr[4], (unsigned long long)fdeg);
+  }
 }
 
 // One BFS level.  slimwork: 0 = every row of every chunk is computed;
 // 1 = chunks whose rows are all final are skipped (Section III-C);
 // 2 = additionally a lane whose row is final issues no loads and the sweep
 // stops at the longest row that is still live.
-template <class S, int U>
-__global__ void level_kernel(LevelArgs a) {
+// The work of one level for one workgroup: stage the LDS prefix, sweep the
+// work units assigned to this workgroup's wavefronts, post-process, count.
+template <class S, int U, bool STAGED>
+__device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units,
+                                           const int32_t* pieces, int64_t n_units,
+                                           uint8_t* lds_stage) {
   const int lane = threadIdx.x & (kC - 1);
   const int wave = threadIdx.x / kC;
   const int waves = blockDim.x / kC;
-
-  // Stop if the previous level discovered nothing, and tell the host what the
-  // previous level found (one thread of the first workgroup).
-  if (a.level > 1) {
-    const uint64_t want = level_tag(a.run_id, a.level - 1);
-    const bool prev_found = (a.any[(a.level - 1) % kRing] == want);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      __hip_atomic_store(&a.report[(a.level - 1) % kRing], (want << 1) | (prev_found ? 1u : 0u),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    if (!prev_found) return;
-  }
-
   const Rsrc rs = S::rsrc(a);
+  Stage st{lds_stage, 0u};
+  if (STAGED) {
+    // copy the vector's first a.lds_bytes (a multiple of 16) into LDS
+    const uint4* src = static_cast<const uint4*>(S::staged(a));
+    uint4* dst = reinterpret_cast<uint4*>(lds_stage);
+    for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    st.bytes = a.lds_bytes;
+  }
   // per-wavefront tallies, flushed once at the end
   uint32_t found = 0, n_chunks = 0;
-  uint64_t n_cols = 0;
+  uint64_t n_cols = 0, fdeg = 0;
   int32_t max_cl = 0;
 
-  for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < a.n_units;
+  for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < n_units;
        u += (int64_t)gridDim.x * waves) {
-    const Unit w = a.units[u];
+    const Unit w = units[u];
     const bool piece = (w.c1 == w.c0 + 1);
     for (int32_t c = w.c0; c < w.c1; ++c) {
       const int32_t row = c * kC + lane;
@@ -355,10 +473,10 @@ __global__ void level_kernel(LevelArgs a) {
       const int32_t ncols = hi > j0 ? hi - j0 : 0;
       n_cols += (uint64_t)ncols;
       const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
-      typename S::Acc acc = sweep<S, U>(a, rs, p, ncols, on);
-      const int32_t npieces = piece ? a.pieces[c] : 1;
+      typename S::Acc acc = sweep<S, U, STAGED>(a, rs, st, p, ncols, on);
+      const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
-        found += finish_rows<S>(a, c, row, acc, lane);
+        found += finish_rows<S>(a, c, row, acc, lane, fdeg);
       } else {
         // SlimChunk: combine this piece, the last one to arrive post-processes.
         // Pieces exchange data only through device-scope atomics: each piece's
@@ -372,23 +490,383 @@ __global__ void level_kernel(LevelArgs a) {
         if (last) {
           acc = S::take(a, row);
           if (lane == 0) a.arrive[c] = 0;
-          found += finish_rows<S>(a, c, row, acc, lane);
+          found += finish_rows<S>(a, c, row, acc, lane, fdeg);
         }
       }
     }
   }
-  if (lane == 0) {
-    if (found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
-    if (a.count_stats && (found | n_chunks | n_cols)) {
-      unsigned long long* ctr =
-          a.counters + ((int64_t)a.level * kCountSlots + (blockIdx.x % kCountSlots)) * kCountFields;
-      if (found) atomicAdd(&ctr[0], (unsigned long long)found);
-      if (n_chunks) {
-        atomicAdd(&ctr[1], (unsigned long long)n_chunks);
-        atomicMax(&ctr[3], (unsigned long long)max_cl);
-      }
-      if (n_cols) atomicAdd(&ctr[2], (unsigned long long)n_cols * kC);
+  if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+  flush_counters(a, lane, found, n_chunks, n_cols * kC, max_cl, fdeg);
+}
+
+
+template <class S, int U, bool STAGED>
+__global__ void level_kernel(LevelArgs a) {
+  extern __shared__ uint8_t lds_stage[];
+
+  const Unit* units = a.units;
+  const int32_t* pieces = a.pieces;
+  int64_t n_units = a.n_units;
+  if (a.variant) {
+    // scheduled level: the schedule kernel has reported the previous level
+    // and chosen this level's variant; only the pull variants run here
+    const int32_t vs = a.variant[a.level % kRing];
+    if (vs < 0 || vs >= kPullVariants) return;
+    units = a.vunits[vs];
+    pieces = a.vpieces[vs];
+    n_units = a.vn_units[vs];
+  } else if (a.level > 1) {
+    // Stop if the previous level discovered nothing, and tell the host what
+    // the previous level found (one thread of the first workgroup).
+    const uint64_t want = level_tag(a.run_id, a.level - 1);
+    const bool prev_found = (a.any[(a.level - 1) % kRing] == want);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      __hip_atomic_store(&a.report[(a.level - 1) % kRing], (want << 1) | (prev_found ? 1u : 0u),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+    if (!prev_found) return;
+  }
+
+  level_body<S, U, STAGED>(a, units, pieces, n_units, lds_stage);
+}
+
+// ------------------------------------------------------- persistent form ---
+//
+// All levels of one run in a single cooperative launch: the grid is no larger
+// than what the device keeps resident at once, levels are separated by a
+// grid barrier, and every workgroup reads the same "found" tag after it, so
+// all leave the loop together.  The barrier's spin has a wall-clock deadline:
+// a workgroup that passes it records an error and returns, so every wave
+// always exits.
+
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, uint64_t limit,
+                                             int* error) {
+  __shared__ int ok;
+  // Every wavefront's stores and atomics of the level must have reached L2
+  // before thread 0 writes L2 back and arrives: the workgroup barrier alone
+  // does not wait for them.
+  wait_memory();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __threadfence();  // release this workgroup's writes of the level
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (atomicAdd(&bar[0], 1u) == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > limit) {
+          atomicExch(error, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();  // acquire the other workgroups' writes
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <class S, int U, bool STAGED>
+__global__ void persistent_kernel(LevelArgs a, void* buf_a, void* buf_b, int32_t cap,
+                                  unsigned* bar, int32_t* status, uint64_t limit) {
+  extern __shared__ uint8_t lds_stage[];
+  for (int32_t k = 1; k <= cap; ++k) {
+    a.level = k;
+    a.vin = (k & 1) ? buf_a : buf_b;
+    a.vout = (k & 1) ? buf_b : buf_a;
+    a.count_stats = a.count_stats && (k <= status[2]);
+    level_body<S, U, STAGED>(a, a.units, a.pieces, a.n_units, lds_stage);
+    if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
+    if (a.any[k % kRing] != level_tag(a.run_id, k)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = k;  // levels run
+      return;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = -1;  // cap reached
+}
+
+// ------------------------------------------------------------ push levels ---
+//
+// The same product computed from the frontier side (the sparse-vector form
+// of Section II-B): every row u of the previous level's frontier queue offers
+// its term to each neighbour w that is still live, through the semiring's
+// atomic; the first offer to w claims it for this level's queue.  A second
+// kernel then post-processes the claimed rows.  Since A is symmetric, row u's
+// cells in the SlimSell layout are its neighbours.
+
+constexpr int kPushLaneMax = 32;    // rows up to this degree are swept by one lane
+constexpr int kPushSegment = 1024;  // longer rows are cut into segments of this many cells
+
+template <class S>
+__device__ __forceinline__ void push_one(const LevelArgs& a, int32_t w, typename S::Acc val,
+                                         int lane) {
+  bool claimed = false;
+  if (w >= 0 && S::live(a, w)) claimed = S::claim(a, w, val);
+  const uint64_t m = __ballot(claimed);
+  if (!m) return;
+  const int leader = __ffsll((long long)m) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(&a.qn[a.level % kRing], (int32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (claimed) a.q_out[base + __popcll(m & lanes_below(lane))] = w;
+}
+
+// Short frontier rows: one lane each.  Long rows are cut into segments of
+// kPushSegment cells that go to the segment list for push_segments_kernel,
+// so a few high-degree rows do not serialise on a few wavefronts.
+template <class S>
+__global__ void push_scatter_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  const int lane = threadIdx.x & (kC - 1);
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kC;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kC;
+  const int32_t nq = a.qn[(a.level - 1) % kRing];
+  uint64_t cells = 0;
+  for (int64_t base = gw * kC; base < nq; base += nw * kC) {
+    const int64_t i = base + lane;
+    const int32_t u = i < nq ? a.q_in[i] : -1;
+    const int32_t du = u >= 0 ? a.deg[u] : 0;
+    const bool big = du > kPushLaneMax;
+    if (u >= 0 && !big) {
+      const int32_t* p = a.col + a.cs[u >> 6] + (u & 63);
+      const typename S::Acc val = S::push_value(a, u);
+      for (int32_t j = 0; j < du; ++j) push_one<S>(a, p[(int64_t)j * kC], val, lane);
+      cells += (uint64_t)du;
+    }
+    // long rows: reserve their segments with one atomic per wavefront
+    const int32_t nseg = big ? (du + kPushSegment - 1) / kPushSegment : 0;
+    int32_t excl = nseg;  // exclusive prefix over the wavefront
+#pragma unroll
+    for (int off = 1; off < kC; off <<= 1) {
+      const int32_t y = __shfl_up(excl, off);
+      if (lane >= off) excl += y;
+    }
+    const int32_t total = __shfl(excl, kC - 1);
+    excl -= nseg;
+    if (total) {
+      int32_t start = 0;
+      if (lane == 0) start = atomicAdd(a.seg_n, total);
+      start = __shfl(start, 0);
+      for (int32_t q = 0; q < nseg; ++q)
+        a.segs[start + excl + q] = make_int2(u, q * kPushSegment);
+    }
+  }
+  flush_counters(a, lane, 0, 0, wave_sum64(cells), 0, 0);
+}
+
+// Long frontier rows, one segment of kPushSegment cells per wavefront pass.
+template <class S>
+__global__ void push_segments_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  const int lane = threadIdx.x & (kC - 1);
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kC;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kC;
+  const int32_t ns = *a.seg_n;
+  uint64_t cells = 0;
+  for (int64_t s = gw; s < ns; s += nw) {
+    const int2 sg = a.segs[s];
+    const int32_t u = sg.x, j0 = sg.y;
+    const int32_t du = a.deg[u];
+    const int32_t j1 = j0 + kPushSegment < du ? j0 + kPushSegment : du;
+    const int32_t* p = a.col + a.cs[u >> 6] + (u & 63);
+    const typename S::Acc val = S::push_value(a, u);
+    for (int32_t j = j0 + lane; j - lane < j1; j += kC)
+      push_one<S>(a, j < j1 ? p[(int64_t)j * kC] : -1, val, lane);
+    cells += (uint64_t)(j1 - j0);
+  }
+  flush_counters(a, lane, 0, 0, lane == 0 ? cells : 0, 0, 0);
+}
+
+template <class S>
+__global__ void push_post_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  const int lane = threadIdx.x & (kC - 1);
+  const int32_t nt = a.qn[a.level % kRing];
+  uint32_t found = 0;
+  uint64_t fdeg = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < nt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const bool mine = i < nt;
+    const int32_t w = mine ? a.q_out[i] : 0;
+    bool fresh = false;
+    if (mine) {
+      fresh = S::post(a, w, S::take(a, w));
+      if (fresh) {
+        S::publish_one(a, w);
+        fdeg += (uint64_t)a.deg[w];
+      }
+    }
+    found += (uint32_t)__popcll(__ballot(fresh));
+  }
+  if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+  flush_counters(a, lane, found, 0, 0, 0, fdeg);
+}
+
+// -------------------------------------------------------------- schedule ---
+//
+// Runs before every scheduled level k: reports level k-1 to the host, stops
+// the run if it found nothing, clears level k's counters and queue, updates
+// the running totals and picks level k's variant from six features of the
+// frontier: by the MLP (6 -> 32 -> 32 -> 4, ReLU; smallest predicted
+// log-time wins) when a model is loaded and gives finite scores, else by the
+// fixed heuristic (pull once the frontier's edges exceed 1/14 of the
+// unvisited edges, otherwise push).
+struct SchedArgs {
+  int32_t level;
+  uint32_t run_id;
+  uint64_t* any;
+  uint64_t* report;
+  int32_t* variant;
+  int32_t* qn;
+  int32_t* seg_n;         // [2] push segment counts by level parity
+  unsigned long long* ring_ctr;
+  double* sums;           // [0] discovered so far, [1] their degrees, [2] previous frontier size
+  const float* model;     // nullptr = no model
+  float* log;             // [log_cap * 12]
+  int32_t log_cap;
+  int32_t mode;           // 1 learned, 2 heuristic, 3.. forced variant (mode - 3)
+  int32_t heuristic_pull; // pull variant used by the heuristic
+  double n, two_m, mean_degree;
+};
+
+__global__ void schedule_kernel(SchedArgs s) {
+  __shared__ float x[kFeatures], h1[32], h2[32], out[kVariants];
+  __shared__ int stop;
+  const int t = threadIdx.x;
+  const int k = s.level;
+  if (t == 0) {
+    stop = 0;
+    if (k > 1) {
+      const uint64_t want = level_tag(s.run_id, k - 1);
+      const bool found = (s.any[(k - 1) % kRing] == want);
+      __hip_atomic_store(&s.report[(k - 1) % kRing], (want << 1) | (found ? 1u : 0u),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (!found) {
+        s.variant[k % kRing] = kStop;
+        stop = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (stop) return;
+  // previous level's totals (16 slots)
+  double nf = 0.0, mf = 0.0;
+  if (t == 0) {
+    const unsigned long long* c = s.ring_ctr + (int64_t)((k - 1) % kRing) * kCountSlots * kCountFields;
+    for (int q = 0; q < kCountSlots; ++q) {
+      nf += (double)c[q * kCountFields + 0];
+      mf += (double)c[q * kCountFields + 4];
+    }
+    if (k > 1) {
+      s.sums[0] += nf;
+      s.sums[1] += mf;
+    }
+    const double nu = s.n - s.sums[0], mu = s.two_m - s.sums[1];
+    const double l2n = log2(s.n > 2.0 ? s.n : 2.0), l2m = log2(1.0 + (s.two_m > 1.0 ? s.two_m : 1.0));
+    const double prev = s.sums[2];
+    double growth = log2((1.0 + nf) / (1.0 + prev)) / 8.0;
+    growth = growth > 1.0 ? 1.0 : (growth < -1.0 ? -1.0 : growth);
+    x[0] = (float)(log2(1.0 + nf) / l2n);
+    x[1] = (float)(log2(1.0 + mf) / l2m);
+    x[2] = (float)(log2(1.0 + (mu > 0.0 ? mu : 0.0)) / l2m);
+    x[3] = (float)((nu > 0.0 ? nu : 0.0) / s.n);
+    x[4] = (float)growth;
+    x[5] = (float)(log2(1.0 + s.mean_degree) / 8.0);
+    s.sums[2] = nf;
+    s.qn[k % kRing] = 0;
+    s.seg_n[k & 1] = 0;  // this level's push segment list starts empty
+    h1[0] = (float)nf;   // stash for the heuristic
+    h2[0] = (float)mf;
+    h2[1] = (float)nu;
+    h2[2] = (float)(mu > 0.0 ? mu : 0.0);
+  }
+  // clear this level's counters
+  unsigned long long* mine = s.ring_ctr + (int64_t)(k % kRing) * kCountSlots * kCountFields;
+  for (int i = t; i < kCountSlots * kCountFields; i += blockDim.x) mine[i] = 0ull;
+  __syncthreads();
+  const float hnf = h1[0], hmf = h2[0], hnu = h2[1], hmu = h2[2];
+  __syncthreads();
+  bool use_model = (s.mode == 1) && s.model;
+  if (use_model) {
+    const float* W1 = s.model;
+    const float* b1 = W1 + 32 * kFeatures;
+    const float* W2 = b1 + 32;
+    const float* b2 = W2 + 32 * 32;
+    const float* W3 = b2 + 32;
+    const float* b3 = W3 + kVariants * 32;
+    if (t < 32) {
+      float acc = b1[t];
+      for (int i = 0; i < kFeatures; ++i) acc += W1[t * kFeatures + i] * x[i];
+      h1[t] = acc > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    if (t < 32) {
+      float acc = b2[t];
+      for (int j = 0; j < 32; ++j) acc += W2[t * 32 + j] * h1[j];
+      h2[t] = acc > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    if (t < kVariants) {
+      float acc = b3[t];
+      for (int j = 0; j < 32; ++j) acc += W3[t * 32 + j] * h2[j];
+      out[t] = acc;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    int32_t v;
+    if (s.mode >= 3) {
+      v = s.mode - 3;
+    } else {
+      bool finite = use_model;
+      if (use_model)
+        for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(out[i]);
+      if (finite) {
+        v = 0;
+        for (int i = 1; i < kVariants; ++i)
+          if (out[i] < out[v]) v = i;
+      } else {
+        // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
+        // pull once the frontier's edges exceed 1/14 of the unvisited edges
+        const bool pull = hmf * 14.0f > hmu;
+        (void)hnf;
+        (void)hnu;
+        v = pull ? s.heuristic_pull : kPush;
+      }
+    }
+    s.variant[k % kRing] = v;
+    if (s.log && k <= s.log_cap) {
+      float* L = s.log + (int64_t)(k - 1) * 12;
+      for (int i = 0; i < kFeatures; ++i) L[i] = x[i];
+      for (int i = 0; i < kVariants; ++i) L[kFeatures + i] = use_model ? out[i] : 0.f;
+      L[10] = (float)v;
+      L[11] = (float)k;
+    }
+  }
+}
+
+// Level-0 state of a scheduled run: the root is the frontier queue, and the
+// synthetic level-0 counters hold one discovered vertex of degree deg(root).
+__global__ void sched_init_kernel(int32_t root_row, const int32_t* deg, int32_t* q0, int32_t* qn,
+                                  unsigned long long* ring_ctr, double* sums) {
+  const int t = threadIdx.x;
+  for (int i = t; i < kCountSlots * kCountFields; i += blockDim.x) ring_ctr[i] = 0ull;
+  __syncthreads();
+  if (t == 0) {
+    const int32_t d = deg[root_row];
+    q0[0] = root_row;
+    qn[0] = 1;
+    ring_ctr[0] = 1ull;
+    ring_ctr[4] = (unsigned long long)d;
+    sums[0] = 1.0;
+    sums[1] = (double)d;
+    sums[2] = 0.0;
+    sums[3] = 0.0;
   }
 }
 
@@ -424,8 +902,12 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
     static_cast<uint8_t*>(vb)[r] = 0;
     acc[r] = 0;
   } else {  // SS_SELMAX: frontier bitmap f_0 = e_r (x_0 = f_0 (.) v), p_0 = x_0
-    if (r < n_chunks)
+    // Both bitmap buffers start clean: a push level adds bits to a buffer
+    // that still holds older bits, which is safe only for bits of this run.
+    if (r < n_chunks) {
       static_cast<uint64_t*>(va)[r] = (r == root_row / kC) ? (1ull << (root_row % kC)) : 0ull;
+      static_cast<uint64_t*>(vb)[r] = 0ull;
+    }
     state[r] = root ? v[r] : (phantom ? -1 : 0);
     acc[r] = 0;
   }
@@ -537,15 +1019,25 @@ int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_
   return check_launch("init_kernel");
 }
 
+template <class S, bool STAGED>
+static void launch_level_u(int waves, int unroll, unsigned grid, const LevelArgs& a,
+                           hipStream_t st) {
+  const size_t lds = STAGED ? a.lds_bytes : 0;
+  if (unroll == 4)
+    level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a);
+  else if (unroll == 16)
+    level_kernel<S, 16, STAGED><<<grid, waves * kC, lds, st>>>(a);
+  else
+    level_kernel<S, 8, STAGED><<<grid, waves * kC, lds, st>>>(a);
+}
+
 template <class S>
 static void launch_level_t(int waves, int unroll, unsigned grid, const LevelArgs& a,
                            hipStream_t st) {
-  if (unroll == 4)
-    level_kernel<S, 4><<<grid, waves * kC, 0, st>>>(a);
-  else if (unroll == 16)
-    level_kernel<S, 16><<<grid, waves * kC, 0, st>>>(a);
+  if (a.lds_bytes)
+    launch_level_u<S, true>(waves, unroll, grid, a, st);
   else
-    level_kernel<S, 8><<<grid, waves * kC, 0, st>>>(a);
+    launch_level_u<S, false>(waves, unroll, grid, a, st);
 }
 
 int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
@@ -564,6 +1056,109 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
     default: return set_error(SS_EINVAL, "unknown semiring");
   }
   return check_launch("level_kernel");
+}
+
+int launch_push(int semiring, const LevelArgs& a, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  constexpr unsigned kGroups = 2048, kThreads = 256;
+  switch (semiring) {
+#define SS_PUSH(S)                                                  \
+  push_scatter_kernel<S><<<kGroups, kThreads, 0, st>>>(a);           \
+  push_segments_kernel<S><<<kGroups, kThreads, 0, st>>>(a);          \
+  push_post_kernel<S><<<kGroups / 2, kThreads, 0, st>>>(a);          \
+  break;
+    case SS_TROPICAL: SS_PUSH(Tropical)
+    case SS_REAL: SS_PUSH(Real)
+    case SS_BOOLEAN: SS_PUSH(Boolean)
+    case SS_SELMAX: SS_PUSH(SelMax)
+#undef SS_PUSH
+    default: return set_error(SS_EINVAL, "push needs a single-root semiring");
+  }
+  return check_launch("push kernels");
+}
+
+int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream) {
+  SchedArgs s;
+  s.level = level;
+  s.run_id = run_id;
+  s.any = p.any;
+  s.report = p.report;
+  s.variant = p.variant;
+  s.qn = p.qn;
+  s.seg_n = p.seg_n;
+  s.ring_ctr = p.ring_ctr;
+  s.sums = p.sums;
+  s.model = p.model;
+  s.log = p.log;
+  s.log_cap = p.log_cap;
+  s.mode = p.mode;
+  s.heuristic_pull = p.heuristic_pull;
+  s.n = p.n;
+  s.two_m = p.two_m;
+  s.mean_degree = p.mean_degree;
+  schedule_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(s);
+  return check_launch("schedule_kernel");
+}
+
+int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream) {
+  sched_init_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(root_row, g.d_deg, ws.q[0],
+                                                                     ws.qn, ws.ring_ctr,
+                                                                     ws.sched_sums);
+  return check_launch("sched_init_kernel");
+}
+
+// The persistent grid is one 1024-thread workgroup per compute unit: a shape
+// every CU can hold at once, so all workgroups are resident and the grid
+// barrier cannot wait on a workgroup that has not started.
+constexpr int kPersistentWaves = 16;
+
+template <class S, bool STAGED>
+static int launch_persistent_u(int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
+                               int32_t cap, unsigned* bar, int32_t* status, uint64_t limit,
+                               int64_t max_groups, hipStream_t st) {
+  const size_t lds = STAGED ? a.lds_bytes : 0;
+  const void* fn = unroll == 4    ? (const void*)persistent_kernel<S, 4, STAGED>
+                   : unroll == 16 ? (const void*)persistent_kernel<S, 16, STAGED>
+                                  : (const void*)persistent_kernel<S, 8, STAGED>;
+  int per_cu = 0, dev = 0, cus = 0, coop = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistentWaves * kC, lds);
+  if (e != hipSuccess) return set_error(SS_EHIP, std::string("occupancy: ") + hipGetErrorString(e));
+  if (!coop) return set_error(SS_EUNSUP, "the device has no cooperative launch");
+  if (per_cu < 1) return set_error(SS_EUNSUP, "persistent kernel does not fit on a compute unit");
+  int64_t grid = cus;
+  if (max_groups > 0 && grid > max_groups) grid = max_groups;
+  LevelArgs aa = a;
+  void* args[] = {&aa, &buf_a, &buf_b, &cap, &bar, &status, &limit};
+  e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kPersistentWaves * kC), args, lds,
+                                 st);
+  if (e != hipSuccess)
+    return set_error(SS_EHIP, std::string("cooperative launch: ") + hipGetErrorString(e));
+  return SS_OK;
+}
+
+int launch_persistent(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
+                      void* buf_a, void* buf_b, int32_t cap, unsigned* bar, int32_t* status,
+                      uint64_t deadline, void* stream) {
+  (void)waves;  // the persistent shape is fixed (see kPersistentWaves)
+  hipStream_t st = static_cast<hipStream_t>(stream);
+#define SS_PERS(S)                                                                          \
+  return a.lds_bytes ? launch_persistent_u<S, true>(unroll, a, buf_a, buf_b, cap, bar, status, \
+                                                     deadline, max_groups, st)                \
+                     : launch_persistent_u<S, false>(unroll, a, buf_a, buf_b, cap, bar, status, \
+                                                      deadline, max_groups, st);
+  switch (semiring) {
+    case SS_TROPICAL: SS_PERS(Tropical)
+    case SS_REAL: SS_PERS(Real)
+    case SS_BOOLEAN: SS_PERS(Boolean)
+    case SS_SELMAX: SS_PERS(SelMax)
+    case kBatchSemiring: SS_PERS(Batch)
+    default: return set_error(SS_EINVAL, "unknown semiring");
+  }
+#undef SS_PERS
 }
 
 int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,

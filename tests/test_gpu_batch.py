@@ -55,7 +55,8 @@ def test_batch_64_roots_one_graph(ss):
     roots = graphgen.pick_roots(e, 64, seed=22)[None, :]
     for mode in (0, 1, 2):
         for split in (0, 64, 1024):
-            G.set_tune(split_len=split)
+            G.set_tune(split_len=split, lds_kib=32 if split == 64 else 0,
+                       max_groups=128 if split == 64 else 0)
             note("batch", mode, split)
             levels, _ = _check_batch(G, [e], [c], roots, slimwork=mode, level_cap=32)
     # per-level discovered rows are counted
@@ -155,3 +156,46 @@ def test_autotune_keeps_results_and_caches(ss):
     rb = G.autotune(roots[None, :], batched=True, repeats=1, force=True)
     assert rb["evaluated"] > 10
     _check_batch(G, [e], [c], roots[None, :].astype(np.int32))
+
+
+def test_persistent_launch_batched_and_single_root(ss):
+    import torch
+    graphs = [graphgen.rmat(12, 16, seed=51), graphgen.er(3000, 20000, seed=52),
+              graphgen.EdgeList(700, np.arange(699, dtype=np.int32),
+                                np.arange(1, 700, dtype=np.int32), "path700")]
+    csrs = [oracle.csr_from_edgelist(g) for g in graphs]
+    G = ss.Graph.from_many(graphs)
+    R = np.full((3, 64), -1, np.int32)
+    for i, g in enumerate(graphs):
+        rr = graphgen.pick_roots(g, 64, seed=53 + i)
+        R[i, :len(rr)] = rr
+    for split, lds in ((0, 0), (64, 32)):
+        G.set_tune(split_len=split, lds_kib=lds, max_groups=0)
+        note("persistent batch", split, lds)
+        levels, runs = _check_batch(G, graphs, csrs, R, persistent=True, level_cap=800,
+                                    timing=True)
+        assert runs["launches"] == 1
+    # single root, every semiring, persistent
+    for i, (g, c) in enumerate(zip(graphs, csrs)):
+        Gs = ss.Graph.from_edgelist(g)
+        roots = graphgen.pick_roots(g, 3, seed=60 + i)
+        for semi in ("tropical", "real", "boolean", "selmax"):
+            note("persistent single", g.name, semi)
+            res = Gs.bfs(roots, semi, persistent=True)
+            torch.cuda.synchronize()
+            for j, r in enumerate(roots):
+                ex = oracle.expected(c, int(r))
+                np.testing.assert_array_equal(res.dist[j].cpu().numpy(), ex.dist)
+                assert int(res.iterations[j]) == ex.iterations
+                if semi == "selmax":
+                    np.testing.assert_array_equal(res.parent[j].cpu().numpy(), ex.parent)
+                if semi == "real":
+                    np.testing.assert_array_equal(res.real_val[j].cpu().numpy(), ex.real_val)
+        with pytest.raises(ss.SlimSellError):
+            Gs.bfs(roots[:1], "selmax", persistent=True, schedule="heuristic")
+        if g.name == "path700":  # the level cap is reported, not hung on
+            with pytest.raises(ss.SlimSellError) as ei:
+                Gs.bfs([0], "boolean", persistent=True, max_levels=2)
+            assert ei.value.code == -5
+        Gs.close()
+    G.close()

@@ -268,6 +268,8 @@ def test_scale22_selmax_split_sweep(ss, kind):
 @pytest.mark.parametrize("tune", [
     dict(unroll=4), dict(unroll=16), dict(max_groups=64), dict(max_groups=7, waves_per_group=2),
     dict(pack_cols=0), dict(pack_cols=40, split_len=96), dict(split_len=0, pack_cols=0),
+    dict(lds_kib=64, max_groups=64), dict(lds_kib=16, max_groups=512, waves_per_group=16),
+    dict(lds_kib=32, unroll=4),
 ])
 def test_launch_configurations_give_identical_results(ss, tune):
     e = graphgen.rmat(13, 16, seed=11)

@@ -1,0 +1,149 @@
+"""GPU tests of the learned per-level schedule: MLP kernels against the
+float64 oracle, training, and exact BFS results under every schedule."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+SEMIS = ["tropical", "real", "boolean", "selmax"]
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2010_09913_amd as mod
+    return mod
+
+
+def note(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_gradient_and_forward_match_the_oracle(ss):
+    rng = np.random.default_rng(1)
+    w = rng.normal(0, 0.3, mlp.PARAMS).astype(np.float32)
+    x = rng.random((777, 6)).astype(np.float32)
+    y = rng.normal(0, 1, (777, 4)).astype(np.float32)
+    loss, g = ss.sched_grad(w, x, y)
+    ref_loss, ref_g = mlp.loss_and_grad(w.astype(np.float64), x.astype(np.float64),
+                                        y.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    np.testing.assert_allclose(g, ref_g, rtol=1e-4, atol=1e-4 * np.abs(ref_g).max())
+    out = ss.sched_forward(w, x)
+    np.testing.assert_allclose(out, mlp.forward(w, x), rtol=1e-5, atol=1e-5)
+
+
+def test_training_reduces_loss_and_is_deterministic(ss):
+    rng = np.random.default_rng(2)
+    teacher = rng.normal(0, 0.5, mlp.PARAMS)
+    x = rng.random((1500, 6)).astype(np.float32)
+    y = mlp.forward(teacher, x).astype(np.float32)
+    w1, l1 = ss.sched_train(x, y, steps=600, lr=3e-3, seed=7)
+    w2, l2 = ss.sched_train(x, y, steps=600, lr=3e-3, seed=7)
+    np.testing.assert_array_equal(w1, w2)
+    assert l1[-1] < 0.1 * l1[0]
+    assert abs(mlp.loss_only(w1, x, y) - l1[-1]) < 0.05 * l1[-1] + 1e-6
+
+
+def _graphs():
+    return {
+        "rmat": graphgen.rmat(13, 16, seed=41),
+        "er": graphgen.er(6000, 30000, seed=42),
+        "grid": graphgen.grid(64, 48, 0.05, seed=5),
+        "path": graphgen.EdgeList(300, np.arange(299, dtype=np.int32),
+                                  np.arange(1, 300, dtype=np.int32), "path300"),
+    }
+
+
+def _run(G, root, semi, schedule):
+    import torch
+    res = G.bfs([root], semi, schedule=schedule, level_cap=4096)
+    torch.cuda.synchronize()
+    return res
+
+
+def _check(res, ex, semi):
+    np.testing.assert_array_equal(res.dist[0].cpu().numpy(), ex.dist)
+    assert int(res.iterations[0]) == ex.iterations
+    if semi == "selmax":
+        np.testing.assert_array_equal(res.parent[0].cpu().numpy(), ex.parent)
+    if semi == "real":
+        np.testing.assert_array_equal(res.real_val[0].cpu().numpy(), ex.real_val)
+
+
+@pytest.mark.parametrize("name", ["rmat", "er", "grid", "path"])
+def test_every_schedule_is_exact_and_features_match(ss, name):
+    e = _graphs()[name]
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e)
+    roots = graphgen.pick_roots(e, 2, seed=43)
+    rng = np.random.default_rng(3)
+    random_model = rng.normal(0, 0.5, mlp.PARAMS).astype(np.float32)
+    pull_v = 1  # the default split length (256) maps to the split-256 pull variant
+    for root in roots:
+        ex = oracle.expected(g, int(root))
+        feats = mlp.features(ex.dist, g.degree, g.n, g.entries)
+        heur = mlp.heuristic(ex.dist, g.degree, g.n, g.entries, pull_v)
+        for semi in SEMIS:
+            for mode in ["heuristic", "pull", "pull-split256", "pull-split1024", "push"]:
+                note(name, root, semi, mode)
+                res = _run(G, int(root), semi, mode)
+                _check(res, ex, semi)
+                it = ex.iterations
+                var = res.levels["variant"][0][:it]
+                if mode == "heuristic":
+                    log = G.sched_log(it)
+                    np.testing.assert_allclose(log[:, :6], feats, rtol=0, atol=2e-6)
+                    np.testing.assert_array_equal(log[:, 11], np.arange(1, it + 1))
+                    # compare the decisions away from ties of the float32 rule
+                    np.testing.assert_array_equal(var, heur)
+                else:
+                    assert np.all(var == ss.VARIANTS.index(mode))
+            # learned: random model -> exact; scores equal the oracle's forward
+            ss.sched_load(random_model)
+            res = _run(G, int(root), semi, "learned")
+            _check(res, ex, semi)
+            log = G.sched_log(ex.iterations)
+            ref = mlp.forward(random_model, log[:, :6])
+            np.testing.assert_allclose(log[:, 6:10], ref, rtol=1e-5, atol=1e-5)
+            srt = np.sort(ref, axis=1)
+            clear = (srt[:, 1] - srt[:, 0]) > 1e-3
+            np.testing.assert_array_equal(log[clear, 10], np.argmin(ref, axis=1)[clear])
+            ss.sched_clear()
+    G.close()
+
+
+def test_model_that_prefers_one_variant_and_nan_fallback(ss):
+    e = _graphs()["rmat"]
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e)
+    root = int(graphgen.pick_roots(e, 1, seed=44)[0])
+    ex = oracle.expected(g, root)
+    for v in range(4):
+        w = np.zeros(mlp.PARAMS, np.float32)
+        w[-4:] = 1.0
+        w[-4 + v] = -1.0                    # b3: variant v always scores lowest
+        ss.sched_load(w)
+        res = _run(G, root, "selmax", "learned")
+        _check(res, ex, "selmax")
+        assert np.all(res.levels["variant"][0][:ex.iterations] == v)
+    w = np.full(mlp.PARAMS, np.nan, np.float32)
+    ss.sched_load(w)
+    res = _run(G, root, "selmax", "learned")
+    _check(res, ex, "selmax")
+    heur = _run(G, root, "selmax", "heuristic")
+    np.testing.assert_array_equal(res.levels["variant"][0], heur.levels["variant"][0])
+    ss.sched_clear()
+    res = _run(G, root, "selmax", "learned")   # no model: heuristic
+    np.testing.assert_array_equal(res.levels["variant"][0], heur.levels["variant"][0])
+    with pytest.raises(ss.SlimSellError):
+        G.bfs([root], "selmax", schedule="heuristic", slimwork=1)
+    with pytest.raises(ss.SlimSellError):
+        ss.sched_load(np.zeros(10, np.float32))
+    G.close()
