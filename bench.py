@@ -57,15 +57,16 @@ def algorithmic_bytes(levels: dict, r: int, iters: int, semi: str, n: int,
     return float(per_level.sum())
 
 
-def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=True):
+def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=True,
+                 schedule=0):
     import torch
     # warm-up (also fixes the per-root component sizes)
     res = None
     for _ in range(warmup):
-        res = G.bfs(roots, semi, split_len=split)
+        res = G.bfs(roots, semi, split_len=split, schedule=schedule)
     torch.cuda.synchronize()
     if res is None:
-        res = G.bfs(roots, semi, split_len=split)
+        res = G.bfs(roots, semi, split_len=split, schedule=schedule)
         torch.cuda.synchronize()
     reached = (res.dist >= 0)
     m_cc = ((reached.to(torch.int64) * deg_t[None, :]).sum(dim=1) // 2).cpu().numpy()
@@ -78,7 +79,7 @@ def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=Tru
     t0 = time.perf_counter()
     runs = []
     for _ in range(steps):
-        r = G.bfs(roots, semi, split_len=split, timing=True)
+        r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule)
         runs.append(r.runs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -313,6 +314,34 @@ def main() -> int:
         }
 
     if not args.only_timed and not args.no_extra:
+        # the same workload with the direction-aware schedules and the autotuner
+        forms = {}
+        for sched in ("heuristic", "learned"):
+            if sched == "learned":
+                from paper_2010_09913_amd import scheduler
+                if not os.path.exists(scheduler.DEFAULT_MODEL):
+                    continue
+                ss.sched_load(np.load(scheduler.DEFAULT_MODEL))
+            o2 = run_workload(ss, G, roots, semi, args.split, max(1, args.steps // 2), 1, deg_t,
+                              count_pass=False, schedule=sched)
+            s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+            forms[sched + "_schedule"] = {"gteps": round(s2["gteps_wall"], 4),
+                                          "gteps_hmean": round(s2["gteps_hmean"], 4),
+                                          "mean_bfs_ms": round(s2["mean_bfs_ms"], 4)}
+            log(f"{sched} schedule: {s2}")
+        ss.sched_clear()
+        default_tune = G.get_tune()
+        t = time.perf_counter()
+        at = G.autotune(roots[:8], semi, repeats=2, force=True)
+        tune_s = time.perf_counter() - t
+        o2 = run_workload(ss, G, roots, semi, -1, max(1, args.steps // 2), 1, deg_t)
+        s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+        forms["autotuned"] = {"gteps": round(s2["gteps_wall"], 4),
+                              "frac": round(s2.get("frac", 0.0), 4), "tune": at["best"],
+                              "configs_timed": at["evaluated"], "tune_s": round(tune_s, 1)}
+        log(f"autotuned {at}: {s2}")
+        G.set_tune(**default_tune)
+        result["forms"] = forms
         sweep = {}
         for split in (0, 256, 1024, 4096):
             o2 = run_workload(ss, G, roots, semi, split, max(1, args.steps // 2), 1, deg_t)

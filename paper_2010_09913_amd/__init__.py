@@ -92,6 +92,17 @@ def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
 
 LEVEL_FIELDS = ("discovered", "frontier_edges", "active_chunks", "active_cells",
                 "max_active_cl", "ms", "variant")
+_LEVEL_DTYPE = np.dtype([("discovered", "<i8"), ("frontier_edges", "<i8"),
+                         ("active_chunks", "<i8"), ("active_cells", "<i8"),
+                         ("max_active_cl", "<i8"), ("ms", "<f4"), ("variant", "<i4")])
+_RUN_DTYPE = np.dtype([("iterations", "<i4"), ("launches", "<i4"), ("kernel_ms", "<f4"),
+                       ("bfs_ms", "<f4")])
+
+
+def _records(buf, dtype, shape):
+    """Copy a ctypes array of records into a dict of numpy arrays."""
+    arr = np.frombuffer(buf, dtype=dtype).reshape(shape)
+    return {f: arr[f].copy() for f in dtype.names}
 VARIANTS = ("pull", "pull-split256", "pull-split1024", "push")
 SCHEDULES = {"none": 0, "learned": 1, "heuristic": 2, "pull": 3, "pull-split256": 4,
              "pull-split1024": 5, "push": 6}
@@ -257,10 +268,9 @@ class Graph:
                                           ptr(dist), ptr(parent), ptr(real_val)))
         levels = run_d = None
         if lvl is not None:
-            levels = {f: np.array([getattr(x, f) for x in lvl]).reshape(nr, level_cap)
-                      for f in LEVEL_FIELDS}
+            levels = _records(lvl, _LEVEL_DTYPE, (nr, level_cap))
         if runs is not None:
-            run_d = {f: np.array([getattr(runs[i], f) for i in range(nr)]) for f in RUN_FIELDS}
+            run_d = {f: v[:nr] for f, v in _records(runs, _RUN_DTYPE, (max(nr, 1),)).items()}
         return BfsResult(dist, parent, real_val, iters[:nr].copy(), levels, run_d)
 
     def bfs_batch(self, roots, *, slimwork: int = 2, max_levels: int = 0, stream=None,
@@ -303,9 +313,9 @@ class Graph:
                                                 ctypes.byref(o), ctypes.c_void_p(dist.data_ptr())))
         levels = run_d = None
         if lvl is not None:
-            levels = {f: np.array([getattr(x, f) for x in lvl]) for f in LEVEL_FIELDS}
+            levels = _records(lvl, _LEVEL_DTYPE, (level_cap,))
         if runs is not None:
-            run_d = {f: getattr(runs[0], f) for f in RUN_FIELDS}
+            run_d = {f: v[0].item() for f, v in _records(runs, _RUN_DTYPE, (1,)).items()}
         return dist, int(iters[0]), levels, run_d
 
     def autotune(self, roots, semiring="selmax", *, batched: bool = False, repeats: int = 3,
