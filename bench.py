@@ -58,15 +58,15 @@ def algorithmic_bytes(levels: dict, r: int, iters: int, semi: str, n: int,
 
 
 def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=True,
-                 schedule=0):
+                 schedule=0, persistent=False):
     import torch
     # warm-up (also fixes the per-root component sizes)
     res = None
     for _ in range(warmup):
-        res = G.bfs(roots, semi, split_len=split, schedule=schedule)
+        res = G.bfs(roots, semi, split_len=split, schedule=schedule, persistent=persistent)
     torch.cuda.synchronize()
     if res is None:
-        res = G.bfs(roots, semi, split_len=split, schedule=schedule)
+        res = G.bfs(roots, semi, split_len=split, schedule=schedule, persistent=persistent)
         torch.cuda.synchronize()
     reached = (res.dist >= 0)
     m_cc = ((reached.to(torch.int64) * deg_t[None, :]).sum(dim=1) // 2).cpu().numpy()
@@ -79,7 +79,8 @@ def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=Tru
     t0 = time.perf_counter()
     runs = []
     for _ in range(steps):
-        r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule)
+        r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule,
+                  persistent=persistent)
         runs.append(r.runs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -123,6 +124,27 @@ def _events_ms(torch, fn, reps=3):
         b.synchronize()
         out.append(a.elapsed_time(b))
     return float(np.median(out))
+
+
+def bench_dp(G, roots, torch) -> dict:
+    """Mean BFS time per root without and with parents: sel-max yields them from
+    the product, the other semirings by the DP transformation after the BFS
+    (the paper's "No-DP" vs "DP")."""
+    out = {}
+    for semi in ("tropical", "real", "boolean", "selmax"):
+        row = {}
+        for dp in (False, True):
+            kw = dict(dp=dp, want_parent=dp, want_real=False)
+            G.bfs(roots, semi, **kw)
+            tot = 0.0
+            for _ in range(2):
+                r = G.bfs(roots, semi, timing=True, **kw)
+                tot += float(r.runs["bfs_ms"].sum())
+            torch.cuda.synchronize()
+            row["dp_ms" if dp else "no_dp_ms"] = round(tot / (2 * len(roots)), 4)
+        out[semi] = row
+        log(f"dp {semi}: {row}")
+    return out
 
 
 def bench_batched(ss, graphgen, torch) -> dict:
@@ -193,14 +215,16 @@ def bench_learned(ss, graphgen, torch) -> dict:
         roots = graphgen.pick_roots(e, nroots, seed=seed)
         G = ss.Graph.from_edgelist(e, sigma=0)
         res = {}
-        for mode in ["learned", "heuristic", "pull", "pull-split256", "pull-split1024", "push"]:
+        for mode in ["learned", "heuristic", "pull", "pull-split256", "pull-split1024", "push",
+                     "learned+persistent", "heuristic+persistent", "push+persistent"]:
+            sched, pers = mode.split("+")[0], mode.endswith("+persistent")
             rr = roots
             if slow_roots and mode.startswith("pull"):
                 rr = roots[:slow_roots]   # pull-only on the grid is O(levels x n): few roots
-            G.bfs([int(rr[0])], "selmax", schedule=mode)
+            G.bfs([int(rr[0])], "selmax", schedule=sched, persistent=pers)
             tot = 0.0
             for r in rr:
-                x = G.bfs([int(r)], "selmax", schedule=mode, timing=True)
+                x = G.bfs([int(r)], "selmax", schedule=sched, timing=True, persistent=pers)
                 tot += float(x.runs["bfs_ms"][0])
             res[mode] = round(tot / len(rr), 3)
             log(f"{name} {mode}: {tot / len(rr):.2f} ms per BFS")
@@ -316,19 +340,22 @@ def main() -> int:
     if not args.only_timed and not args.no_extra:
         # the same workload with the direction-aware schedules and the autotuner
         forms = {}
-        for sched in ("heuristic", "learned"):
+        for sched, pers in (("none", True), ("heuristic", False), ("heuristic", True),
+                            ("learned", False), ("learned", True)):
             if sched == "learned":
                 from paper_2010_09913_amd import scheduler
                 if not os.path.exists(scheduler.DEFAULT_MODEL):
                     continue
                 ss.sched_load(np.load(scheduler.DEFAULT_MODEL))
             o2 = run_workload(ss, G, roots, semi, args.split, max(1, args.steps // 2), 1, deg_t,
-                              count_pass=False, schedule=sched)
+                              count_pass=False, schedule=sched, persistent=pers)
             s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
-            forms[sched + "_schedule"] = {"gteps": round(s2["gteps_wall"], 4),
-                                          "gteps_hmean": round(s2["gteps_hmean"], 4),
-                                          "mean_bfs_ms": round(s2["mean_bfs_ms"], 4)}
-            log(f"{sched} schedule: {s2}")
+            name = ("pull" if sched == "none" else sched + "_schedule") + (
+                "_persistent" if pers else "")
+            forms[name] = {"gteps": round(s2["gteps_wall"], 4),
+                           "gteps_hmean": round(s2["gteps_hmean"], 4),
+                           "mean_bfs_ms": round(s2["mean_bfs_ms"], 4)}
+            log(f"{name}: {s2}")
         ss.sched_clear()
         default_tune = G.get_tune()
         t = time.perf_counter()
@@ -350,6 +377,7 @@ def main() -> int:
                                  "frac": round(s2.get("frac", 0.0), 4)}
             log(f"split {split}: {s2}")
         result["split_sweep"] = sweep
+        result["dp"] = bench_dp(G, roots[:16], torch)
         G.close()
         # Erdos-Renyi graph of the same size (mean degree 32)
         er = graphgen.er(1 << args.scale, 16 << args.scale, seed=2)

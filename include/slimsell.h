@@ -253,8 +253,11 @@ typedef struct {
 /* Run all levels of a BFS in one cooperative (persistent) kernel launch with a
  * device-wide barrier between levels, instead of one launch per level: one
  * 1024-thread workgroup per compute unit (capped by the graph's max_groups).
- * Needs schedule = 0.  Per-level times are not available in this mode; a
- * barrier that waits more than 5 s is reported as SS_EHIP. */
+ * With a schedule, every workgroup computes each level's variant from the
+ * same counters and the push phases (scatter, long-row segments, post) are
+ * separated by device-wide barriers too; results and per-level variants are
+ * those of the launch-per-level form.  Per-level times are not available in
+ * this mode; a barrier that waits more than 5 s is reported as SS_EHIP. */
 #define SS_RUN_PERSISTENT 4
 
 /*
@@ -317,17 +320,39 @@ typedef struct {
  *   roots     : host int32[num_roots], each in [0, n).
  *   dist      : device int32[num_roots * n]; row r receives hop distances from
  *               roots[r] (-1 = unreachable).  Required.
- *   parent    : device int32[num_roots * n] or NULL; SS_SELMAX only (the
- *               sel-max product yields parents: the largest-ID neighbour one
- *               level closer; parent[root] = root; -1 = unreachable).
+ *   parent    : device int32[num_roots * n] or NULL: the largest-ID
+ *               neighbour one level closer; parent[root] = root; -1 =
+ *               unreachable.  SS_SELMAX yields it from the product itself;
+ *               the other semirings run the DP transformation
+ *               (slimsell_dp_parents) after each root's BFS, inside the
+ *               timed region (Section II-B; "DP" vs "No-DP").
  *   real_val  : device float[num_roots * n] or NULL; SS_REAL only: the
  *               real-semiring value x_{d(v)}^v at discovery, i.e. the number
  *               of neighbours one level closer (root 1, unreachable 0).
- * Errors: SS_EINVAL (root out of range, parent with a non-sel-max semiring,
- * real_val with a non-real semiring, bad options), SS_EITER, SS_EHIP.
+ * Errors: SS_EINVAL (root out of range, real_val with a non-real semiring,
+ * bad options), SS_EITER, SS_EHIP.
  */
 int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiring s,
                  const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
+
+/*
+ * DP transformation (Section II-B): parents from BFS distances.  For every
+ * vertex v with dist[v] >= 1, parent[v] = the largest original ID u among
+ * v's neighbours with dist[u] = dist[v] - 1 (-1 if there is none); a vertex
+ * with dist 0 is its own parent; dist < 0 gives -1.  One sweep of the
+ * SlimSell layout per root that gathers dist mod 3 as a 2-bit code (a
+ * neighbour is one level closer, at the same level or one further, so the
+ * code decides), so the input must be BFS distances on this graph (other
+ * input gives unspecified parents, never an out-of-bounds access).
+ *   dist      : device int32[num_roots * n], original vertex order (as
+ *               slimsell_bfs or slimsell_bfs_batch write it).
+ *   parent    : device int32[num_roots * n], written.
+ *   stream    : hipStream_t.  Uses the graph's workspace: calls on one graph
+ *               must be ordered (one stream), as for slimsell_bfs.
+ * Errors: SS_EINVAL (NULL graph/pointers, num_roots < 0), SS_EHIP.
+ */
+int slimsell_dp_parents(ss_graph* g, const int32_t* dist, int32_t num_roots, int32_t* parent,
+                        void* stream);
 
 /* ------------------------------------------------------- learned schedule */
 
@@ -338,8 +363,9 @@ int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiri
  * floats): W1[32][6], b1[32], W2[32][32], b2[32], W3[4][32], b3[4].
  * Features, in order: log2(1+n_f)/log2 n; log2(1+m_f)/log2(1+2m);
  * log2(1+m_u)/log2(1+2m); n_u/n; clamp(log2((1+n_f)/(1+n_f,prev))/8, +-1);
- * log2(1+2m/n)/8 -- n_f, m_f: vertices and edges of the frontier; n_u, m_u:
- * vertices and edges not yet discovered; m: undirected edges.
+ * clamp(log2((1+m_f)/(1+m_u))/16, +-1) -- n_f, m_f: vertices and edges of
+ * the frontier; n_u, m_u: vertices and edges not yet discovered; m:
+ * undirected edges.  All are ratios, so they carry across graph sizes.
  */
 #define SS_SCHED_PARAMS 1412
 #define SS_SCHED_FEATURES 6

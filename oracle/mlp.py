@@ -87,9 +87,9 @@ def features(dist, degree, n: int, entries: int):
         mu = float(entries - deg[before].sum())
         prev = float((dist == k - 2).sum()) if k >= 2 else 0.0
         growth = np.clip(np.log2((1.0 + nf) / (1.0 + prev)) / 8.0, -1.0, 1.0)
+        ratio = np.clip(np.log2((1.0 + mf) / (1.0 + max(mu, 0.0))) / 16.0, -1.0, 1.0)
         rows.append([np.log2(1.0 + nf) / l2n, np.log2(1.0 + mf) / l2m,
-                     np.log2(1.0 + max(mu, 0.0)) / l2m, max(nu, 0.0) / n, growth,
-                     np.log2(1.0 + entries / n) / 8.0])
+                     np.log2(1.0 + max(mu, 0.0)) / l2m, max(nu, 0.0) / n, growth, ratio])
     return np.array(rows)
 
 

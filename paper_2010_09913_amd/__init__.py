@@ -215,9 +215,11 @@ class Graph:
             waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
             level_cap: int = 0, timing: bool = False, counters: bool = None,
             persistent: bool = False, want_parent: bool = True, want_real: bool = True,
-            dist=None, parent=None, real_val=None) -> BfsResult:
+            dp: bool = False, dist=None, parent=None, real_val=None) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
+        Sel-max returns parents (unless want_parent=False); dp=True gives the
+        other semirings parents too, by the DP transformation after each BFS.
         level_cap > 0 records per-level statistics (fused counters unless
         counters=False); timing=True adds event timings per level and per root.
         """
@@ -233,7 +235,7 @@ class Graph:
                                  f"num_roots * n = {nr * self.n} elements")
         if dist is None:
             dist = torch.empty((nr, self.n), dtype=torch.int32, device=dev)
-        if parent is None and want_parent and s == SELMAX:
+        if parent is None and ((want_parent and s == SELMAX) or dp):
             parent = torch.empty((nr, self.n), dtype=torch.int32, device=dev)
         if real_val is None and want_real and s == REAL:
             real_val = torch.empty((nr, self.n), dtype=torch.float32, device=dev)
@@ -272,6 +274,24 @@ class Graph:
         if runs is not None:
             run_d = {f: v[:nr] for f, v in _records(runs, _RUN_DTYPE, (max(nr, 1),)).items()}
         return BfsResult(dist, parent, real_val, iters[:nr].copy(), levels, run_d)
+
+    def dp_parents(self, dist, parent=None, stream=None):
+        """Parents from BFS distances (DP transformation): dist is an int32
+        device tensor of num_roots * n elements in original vertex order."""
+        import torch
+        if dist.dtype != torch.int32 or not dist.is_cuda or not dist.is_contiguous() or \
+                dist.numel() % max(self.n, 1):
+            raise ValueError("dist must be a contiguous int32 device tensor of num_roots * n")
+        nr = dist.numel() // max(self.n, 1)
+        if parent is None:
+            parent = torch.empty_like(dist)
+        elif parent.dtype != torch.int32 or not parent.is_cuda or not parent.is_contiguous() \
+                or parent.numel() != dist.numel():
+            raise ValueError("parent must match dist")
+        check(_native.load().slimsell_dp_parents(self._h, ctypes.c_void_p(dist.data_ptr()), nr,
+                                                 ctypes.c_void_p(parent.data_ptr()),
+                                                 _stream_handle(stream)))
+        return parent
 
     def bfs_batch(self, roots, *, slimwork: int = 2, max_levels: int = 0, stream=None,
                   level_cap: int = 0, timing: bool = False, counters: bool = None,

@@ -27,7 +27,7 @@ EXPORTS = [
     "slimsell_bfs", "slimsell_sync", "slimsell_last_error", "slimsell_version",
     "slimsell_build_multi", "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
     "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log", "slimsell_sched_grad",
-    "slimsell_sched_forward", "slimsell_sched_train",
+    "slimsell_sched_forward", "slimsell_sched_train", "slimsell_dp_parents",
 ]
 SCHED_PARAMS, SCHED_FEATURES, SCHED_VARIANTS = 1412, 6, 4
 
@@ -143,6 +143,7 @@ def load() -> ctypes.CDLL:
     lib.slimsell_sched_train.argtypes = [c_f32p, c_f32p, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_float, ctypes.c_uint64, c_f32p, c_f32p, c_f32p,
                                          vp]
+    lib.slimsell_dp_parents.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     lib.slimsell_last_error.argtypes = []
     lib.slimsell_last_error.restype = ctypes.c_char_p
     lib.slimsell_version.argtypes = []
@@ -153,7 +154,8 @@ def load() -> ctypes.CDLL:
                  "slimsell_bfs", "slimsell_sync", "slimsell_build_multi",
                  "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
                  "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log",
-                 "slimsell_sched_grad", "slimsell_sched_forward", "slimsell_sched_train"):
+                 "slimsell_sched_grad", "slimsell_sched_forward", "slimsell_sched_train",
+                 "slimsell_dp_parents"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -27,6 +27,7 @@ SOURCES = [
     ("api.hip", DEVICE_FLAGS),
     ("autotune.hip", DEVICE_FLAGS),
     ("sched.hip", DEVICE_FLAGS),
+    ("dp.hip", DEVICE_FLAGS),
 ]
 
 

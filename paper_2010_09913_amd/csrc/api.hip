@@ -308,7 +308,6 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT))
     return set_error(SS_EINVAL, "bad flags");
   p->persistent = (o->flags & SS_RUN_PERSISTENT) != 0;
-  if (p->persistent && o->schedule) return set_error(SS_EINVAL, "persistent runs need schedule = 0");
   p->slimwork = o->slimwork;
   p->lds_bytes = 0;
   if (g.tune.lds_kib > 0) {
@@ -404,6 +403,27 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
 // The level loop of one BFS run: level kernels are enqueued kLookahead ahead
 // of the level being waited on; the run ends at the first level that
 // discovers nothing.
+// Schedule parameters that stay fixed over one run.
+static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
+  SchedLaunch sl;
+  std::memset(&sl, 0, sizeof(sl));
+  sl.any = g.ws.any;
+  sl.report = g.ws.d_report;
+  sl.variant = g.ws.variant;
+  sl.qn = g.ws.qn;
+  sl.seg_n = g.ws.seg_n;
+  sl.ring_ctr = g.ws.ring_ctr;
+  sl.sums = g.ws.sched_sums;
+  sl.model = p.has_model ? g.ws.model : nullptr;
+  sl.log = g.ws.sched_log;
+  sl.log_cap = (int32_t)g.ws.sched_log_cap;
+  sl.mode = p.schedule;
+  sl.heuristic_pull = g.tune.split_len == 0 ? 0 : (g.tune.split_len <= 512 ? 1 : 2);
+  sl.n = (double)g.n;
+  sl.two_m = (double)g.entries;
+  return sl;
+}
+
 static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, void* buf_a,
                           void* buf_b, hipStream_t st, RunLog* log, int32_t run_idx) {
   int rc;
@@ -423,9 +443,17 @@ static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, v
     if ((rc = pool_event(g, log->next_ev++, &e1))) return rc;
     SS_HIP(hipEventRecord(e0, st));
   }
-  rc = launch_persistent(policy, p.waves, p.unroll, p.max_groups, a, buf_a, buf_b,
-                         (int32_t)std::min<int64_t>(p.cap, INT32_MAX), g.ws.bar, g.ws.pstatus,
-                         limit, st);
+  const SchedLaunch sl = sched_launch(g, p);
+  PersistentRun pr;
+  pr.cap = (int32_t)std::min<int64_t>(p.cap, INT32_MAX);
+  pr.max_groups = p.max_groups;
+  pr.bar = g.ws.bar;
+  pr.status = g.ws.pstatus;
+  pr.limit = limit;
+  pr.sched = p.schedule ? &sl : nullptr;
+  pr.q0 = g.ws.q[0];
+  pr.q1 = g.ws.q[1];
+  rc = launch_persistent(policy, p.unroll, a, buf_a, buf_b, pr, st);
   if (rc) return rc;
   if (p.timing) SS_HIP(hipEventRecord(e1, st));
   int32_t status[4] = {0, 0, 0, 0};
@@ -443,25 +471,7 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
   if (p.persistent) return run_persistent(g, p, policy, a, buf_a, buf_b, st, log, run_idx);
   constexpr int kLookahead = 2;
   int32_t launched = 0;
-  SchedLaunch sl;
-  std::memset(&sl, 0, sizeof(sl));
-  if (p.schedule) {
-    sl.any = g.ws.any;
-    sl.report = g.ws.d_report;
-    sl.variant = g.ws.variant;
-    sl.qn = g.ws.qn;
-    sl.seg_n = g.ws.seg_n;
-    sl.ring_ctr = g.ws.ring_ctr;
-    sl.sums = g.ws.sched_sums;
-    sl.model = p.has_model ? g.ws.model : nullptr;
-    sl.log = g.ws.sched_log;
-    sl.log_cap = (int32_t)g.ws.sched_log_cap;
-    sl.mode = p.schedule;
-    sl.heuristic_pull = g.tune.split_len == 0 ? 0 : (g.tune.split_len <= 512 ? 1 : 2);
-    sl.n = (double)g.n;
-    sl.two_m = (double)g.entries;
-    sl.mean_degree = g.n ? (double)g.entries / (double)g.n : 0.0;
-  }
+  const SchedLaunch sl = sched_launch(g, p);
   auto launch = [&](int32_t k) -> int {
     a.level = k;
     a.vin = (k & 1) ? buf_a : buf_b;
@@ -809,7 +819,6 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   if (num_roots == 0) return SS_OK;
   if (!roots || !dist) return set_error(SS_EINVAL, "roots and dist are required");
   if ((int)s < 0 || (int)s > 3) return set_error(SS_EINVAL, "unknown semiring");
-  if (parent && s != SS_SELMAX) return set_error(SS_EINVAL, "parent needs SS_SELMAX");
   if (real_val && s != SS_REAL) return set_error(SS_EINVAL, "real_val needs SS_REAL");
   for (int32_t r = 0; r < num_roots; ++r)
     if (roots[r] < 0 || roots[r] >= g.n) return set_error(SS_EINVAL, "root out of range [0, n)");
@@ -832,13 +841,42 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     rc = run_levels(g, plan, (int)s, a, g.ws.vec_a, g.ws.vec_b, st, &log, r);
     if (rc) return rc;
     if (o->iterations_out) o->iterations_out[r] = log.iters[r];
-    rc = launch_finalise(s, g, g.ws, dist + (int64_t)r * g.n,
-                         parent ? parent + (int64_t)r * g.n : nullptr,
+    int32_t* dist_r = dist + (int64_t)r * g.n;
+    int32_t* parent_r = parent ? parent + (int64_t)r * g.n : nullptr;
+    rc = launch_finalise(s, g, g.ws, dist_r, s == SS_SELMAX ? parent_r : nullptr,
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
+    // the other semirings get parents by the DP transformation (Section II-B)
+    if (parent_r && s != SS_SELMAX &&
+        (rc = launch_dp(g, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r, parent_r,
+                        st)))
+      return rc;
     if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
   }
   return collect_stats(g, o, plan, num_roots, log, st);
+}
+
+int slimsell_dp_parents(ss_graph* gp, const int32_t* dist, int32_t num_roots, int32_t* parent,
+                        void* stream) {
+  if (!gp) return set_error(SS_EINVAL, "graph is NULL");
+  if (num_roots < 0) return set_error(SS_EINVAL, "num_roots < 0");
+  if (num_roots == 0) return SS_OK;
+  if (!dist || !parent) return set_error(SS_EINVAL, "dist and parent are required");
+  Graph& g = *gp;
+  std::lock_guard<std::mutex> lock(g.mu);
+  SS_HIP(hipSetDevice(g.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t split = g.tune.split_len;
+  const int32_t pack = g.tune.pack_cols < 0 ? (split > 0 ? split : 0) : g.tune.pack_cols;
+  UnitList* ul = nullptr;
+  int rc = get_units(g, split, pack, &ul);
+  if (rc) return rc;
+  for (int32_t r = 0; r < num_roots; ++r) {
+    rc = launch_dp(g, *ul, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
+                   dist + (int64_t)r * g.n, parent + (int64_t)r * g.n, st);
+    if (rc) return rc;
+  }
+  return SS_OK;
 }
 
 int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss_bfs_opts* o,

@@ -18,6 +18,13 @@ constexpr int32_t kInf = 0x7FFFFFFE; // tropical infinity; kInf + 1 does not ove
 
 int set_error(int code, const std::string& msg);
 
+// SS_EHIP with the launch error, if the last kernel launch failed.
+inline int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(SS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return SS_OK;
+}
+
 // Process-wide scheduler model (slimsell_sched_load); version 0 = none.
 bool sched_model(std::vector<float>* out, uint64_t* version);
 
@@ -207,15 +214,33 @@ struct SchedLaunch {
   int32_t log_cap;
   int32_t mode;
   int32_t heuristic_pull;
-  double n, two_m, mean_degree;
+  double n, two_m;
+};
+
+// One run in a single cooperative launch: level cap, grid barrier words,
+// status words ([0] levels run or -1 at the cap, [1] barrier timed out,
+// [2] level-statistics cap), barrier deadline in wall-clock ticks; with
+// `sched` set, the scheduled form with frontier queues q0/q1.
+struct PersistentRun {
+  int32_t cap;
+  int64_t max_groups;
+  unsigned* bar;
+  int32_t* status;
+  uint64_t limit;
+  const SchedLaunch* sched;
+  int32_t* q0;
+  int32_t* q1;
 };
 
 // Kernel launchers (kernels.hip).
 int launch_push(int semiring, const LevelArgs& a, void* stream);
-int launch_persistent(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
-                      void* buf_a, void* buf_b, int32_t cap, unsigned* bar, int32_t* status,
-                      uint64_t deadline, void* stream);
+int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
+                      const PersistentRun& r, void* stream);
 int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream);
+// DP transformation (dp.hip): parents (original IDs) from distances (original
+// IDs) of one root, through the workspace's d, g and acc buffers.
+int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t max_groups,
+              const int32_t* dist, int32_t* parent, void* stream);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,

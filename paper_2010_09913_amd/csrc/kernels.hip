@@ -21,6 +21,7 @@
 // row that is still undiscovered.
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "internal.h"
 
 namespace ss {
@@ -42,17 +43,6 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // atomic used to merge SlimChunk pieces; post(row, acc), the per-semiring
 // post-processing of the listing in Section III-A; and publish(chunk, mask),
 // which stores the chunk's new frontier word where the frontier is a bitmap.
-
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr uint32_t kOob = 0x80000000u;  // any offset >= the buffer size reads as 0
-constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
-
-__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
-}
-__device__ __forceinline__ uint32_t off_of(int32_t c, int shift) {
-  return c >= 0 ? ((uint32_t)c << shift) : kOob;
-}
 
 // LDS-staged prefix of the gathered vector.  With a full sort the rows of
 // highest degree (the most gathered) come first, so each workgroup copies the
@@ -94,13 +84,11 @@ __device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint3
   return (in ? l : 0ull) | g;
 }
 
-// Returning atomics, so that the wait that follows covers their completion.
-__device__ __forceinline__ void keep(int32_t v) { asm volatile("" ::"v"(v)); }
-__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Tropical (min, +): x_k = f_k = A' (x) f_{k-1}, A' has 1 on edges, 0 on the
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
+  static constexpr bool kSingleRoot = true;
   using Acc = int32_t;
   __device__ static Acc identity() { return kInf; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
@@ -144,6 +132,7 @@ struct Tropical {
 // the row enters the frontier.  Sums of 0/1 values of at most the degree are
 // exact in fp32.
 struct Real {
+  static constexpr bool kSingleRoot = true;
   using Acc = float;
   __device__ static Acc identity() { return 0.0f; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
@@ -187,6 +176,7 @@ struct Real {
 
 // Boolean (|, &): x_k = A (x) f_{k-1}; f_k = x_k & g_k with a uint8 frontier.
 struct Boolean {
+  static constexpr bool kSingleRoot = true;
   using Acc = uint32_t;
   __device__ static Acc identity() { return 0u; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
@@ -234,6 +224,7 @@ struct Boolean {
 // v.  A gather tests one bit and reads v only on a hit, so the product is
 // evaluated exactly while the gathered array is 32 times smaller.
 struct SelMax {
+  static constexpr bool kSingleRoot = true;
   using Acc = int32_t;
   __device__ static Acc identity() { return 0; }
   __device__ static Rsrc rsrc(const LevelArgs& a) {
@@ -290,6 +281,7 @@ struct SelMax {
 // recorded in the row's 64 x 16-bit level record.  A row is final once every
 // slot its graph uses has reached it.
 struct Batch {
+  static constexpr bool kSingleRoot = false;
   using Acc = unsigned long long;
   __device__ static Acc identity() { return 0ull; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 8u); }
@@ -329,14 +321,6 @@ struct Batch {
 
 // ---------------------------------------------------------- level kernel ---
 
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int32_t o = __shfl_xor(v, off);
-    v = o > v ? o : v;
-  }
-  return v;
-}
 
 // Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
 // U independent streaming loads of `col`, then the U gathers of the block.  A
@@ -619,13 +603,15 @@ __device__ __forceinline__ void push_one(const LevelArgs& a, int32_t w, typename
 // Short frontier rows: one lane each.  Long rows are cut into segments of
 // kPushSegment cells that go to the segment list for push_segments_kernel,
 // so a few high-degree rows do not serialise on a few wavefronts.
+// The push phases are written for any grid: wavefront `gw` of `nw`.
+__device__ __forceinline__ int32_t load_count(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class S>
-__global__ void push_scatter_kernel(LevelArgs a) {
-  if (a.variant[a.level % kRing] != kPush) return;
+__device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw, int64_t nw) {
   const int lane = threadIdx.x & (kC - 1);
-  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kC;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kC;
-  const int32_t nq = a.qn[(a.level - 1) % kRing];
+  const int32_t nq = load_count(&a.qn[(a.level - 1) % kRing]);
   uint64_t cells = 0;
   for (int64_t base = gw * kC; base < nq; base += nw * kC) {
     const int64_t i = base + lane;
@@ -661,12 +647,9 @@ __global__ void push_scatter_kernel(LevelArgs a) {
 
 // Long frontier rows, one segment of kPushSegment cells per wavefront pass.
 template <class S>
-__global__ void push_segments_kernel(LevelArgs a) {
-  if (a.variant[a.level % kRing] != kPush) return;
+__device__ __forceinline__ void push_segments_body(const LevelArgs& a, int64_t gw, int64_t nw) {
   const int lane = threadIdx.x & (kC - 1);
-  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kC;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kC;
-  const int32_t ns = *a.seg_n;
+  const int32_t ns = load_count(a.seg_n);
   uint64_t cells = 0;
   for (int64_t s = gw; s < ns; s += nw) {
     const int2 sg = a.segs[s];
@@ -682,15 +665,15 @@ __global__ void push_segments_kernel(LevelArgs a) {
   flush_counters(a, lane, 0, 0, lane == 0 ? cells : 0, 0, 0);
 }
 
+// Post-process the rows claimed this level: lane `lane` of wavefront `gw`
+// of `nw` takes queue entries gw*64+lane, (gw+nw)*64+lane, ...
 template <class S>
-__global__ void push_post_kernel(LevelArgs a) {
-  if (a.variant[a.level % kRing] != kPush) return;
+__device__ __forceinline__ void push_post_body(const LevelArgs& a, int64_t gw, int64_t nw) {
   const int lane = threadIdx.x & (kC - 1);
-  const int32_t nt = a.qn[a.level % kRing];
+  const int32_t nt = load_count(&a.qn[a.level % kRing]);
   uint32_t found = 0;
   uint64_t fdeg = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < nt;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = gw * kC + lane; i - lane < nt; i += nw * kC) {
     const bool mine = i < nt;
     const int32_t w = mine ? a.q_out[i] : 0;
     bool fresh = false;
@@ -705,6 +688,31 @@ __global__ void push_post_kernel(LevelArgs a) {
   }
   if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
   flush_counters(a, lane, found, 0, 0, 0, fdeg);
+}
+
+__device__ __forceinline__ int64_t grid_wave() {
+  return ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kC;
+}
+__device__ __forceinline__ int64_t grid_waves() { return ((int64_t)gridDim.x * blockDim.x) / kC; }
+
+// Launched after the pull kernel of every scheduled level; they return at
+// once unless the level's variant is push.
+template <class S>
+__global__ void push_scatter_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  push_scatter_body<S>(a, grid_wave(), grid_waves());
+}
+
+template <class S>
+__global__ void push_segments_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  push_segments_body<S>(a, grid_wave(), grid_waves());
+}
+
+template <class S>
+__global__ void push_post_kernel(LevelArgs a) {
+  if (a.variant[a.level % kRing] != kPush) return;
+  push_post_body<S>(a, grid_wave(), grid_waves());
 }
 
 // -------------------------------------------------------------- schedule ---
@@ -731,11 +739,132 @@ struct SchedArgs {
   int32_t log_cap;
   int32_t mode;           // 1 learned, 2 heuristic, 3.. forced variant (mode - 3)
   int32_t heuristic_pull; // pull variant used by the heuristic
-  double n, two_m, mean_degree;
+  double n, two_m;        // vertices, directed edges (2m)
 };
 
+// Workgroup scratch of the schedule.  `sums` are the running totals: [0]
+// vertices discovered so far, [1] their degrees, [2] the previous frontier's
+// size.
+struct SchedShared {
+  float x[kFeatures], h1[32], h2[32], out[kVariants];
+  double sums[3];
+  float mf, mu;
+  int32_t v;
+};
+
+// Level k's variant, from level k-1's counters, computed by a whole
+// workgroup (at least 32 threads; every thread must call it).  Advances
+// `sh.sums` past level k-1.  A `writer` workgroup records the decision in
+// the variant ring and the schedule log.  The arithmetic is the same in every
+// workgroup, so all workgroups that call it with the same counters agree.
+__device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh, bool writer) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double nf = 0.0, mf = 0.0;
+    const unsigned long long* c =
+        s.ring_ctr + (int64_t)((k - 1) % kRing) * kCountSlots * kCountFields;
+    for (int q = 0; q < kCountSlots; ++q) {
+      nf += (double)__hip_atomic_load(&c[q * kCountFields + 0], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+      mf += (double)__hip_atomic_load(&c[q * kCountFields + 4], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (k > 1) {
+      sh.sums[0] += nf;
+      sh.sums[1] += mf;
+    }
+    const double nu = s.n - sh.sums[0], mu = s.two_m - sh.sums[1];
+    const double l2n = log2(s.n > 2.0 ? s.n : 2.0), l2m = log2(1.0 + (s.two_m > 1.0 ? s.two_m : 1.0));
+    double growth = log2((1.0 + nf) / (1.0 + sh.sums[2])) / 8.0;
+    growth = growth > 1.0 ? 1.0 : (growth < -1.0 ? -1.0 : growth);
+    const double mu0 = mu > 0.0 ? mu : 0.0;
+    double ratio = log2((1.0 + mf) / (1.0 + mu0)) / 16.0;
+    ratio = ratio > 1.0 ? 1.0 : (ratio < -1.0 ? -1.0 : ratio);
+    sh.x[0] = (float)(log2(1.0 + nf) / l2n);
+    sh.x[1] = (float)(log2(1.0 + mf) / l2m);
+    sh.x[2] = (float)(log2(1.0 + mu0) / l2m);
+    sh.x[3] = (float)((nu > 0.0 ? nu : 0.0) / s.n);
+    sh.x[4] = (float)growth;
+    sh.x[5] = (float)ratio;
+    sh.sums[2] = nf;
+    sh.mf = (float)mf;
+    sh.mu = (float)mu0;
+  }
+  __syncthreads();
+  const bool use_model = (s.mode == 1) && s.model;
+  if (use_model) {
+    const float* W1 = s.model;
+    const float* b1 = W1 + 32 * kFeatures;
+    const float* W2 = b1 + 32;
+    const float* b2 = W2 + 32 * 32;
+    const float* W3 = b2 + 32;
+    const float* b3 = W3 + kVariants * 32;
+    if (t < 32) {
+      float acc = b1[t];
+      for (int i = 0; i < kFeatures; ++i) acc += W1[t * kFeatures + i] * sh.x[i];
+      sh.h1[t] = acc > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    if (t < 32) {
+      float acc = b2[t];
+      for (int j = 0; j < 32; ++j) acc += W2[t * 32 + j] * sh.h1[j];
+      sh.h2[t] = acc > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    if (t < kVariants) {
+      float acc = b3[t];
+      for (int j = 0; j < 32; ++j) acc += W3[t * 32 + j] * sh.h2[j];
+      sh.out[t] = acc;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    int32_t v;
+    if (s.mode >= 3) {
+      v = s.mode - 3;
+    } else {
+      bool finite = use_model;
+      if (use_model)
+        for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(sh.out[i]);
+      if (finite) {
+        v = 0;
+        for (int i = 1; i < kVariants; ++i)
+          if (sh.out[i] < sh.out[v]) v = i;
+      } else {
+        // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
+        // pull once the frontier's edges exceed 1/14 of the unvisited edges
+        v = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
+      }
+    }
+    sh.v = v;
+    if (writer) {
+      s.variant[k % kRing] = v;
+      if (s.log && k <= s.log_cap) {
+        float* L = s.log + (int64_t)(k - 1) * 12;
+        for (int i = 0; i < kFeatures; ++i) L[i] = sh.x[i];
+        for (int i = 0; i < kVariants; ++i) L[kFeatures + i] = use_model ? sh.out[i] : 0.f;
+        L[10] = (float)v;
+        L[11] = (float)k;
+      }
+    }
+  }
+  __syncthreads();
+  return sh.v;
+}
+
+// Clear what level k accumulates into: its counters, queue length and push
+// segment count (one workgroup).
+__device__ __forceinline__ void sched_clear_level(const SchedArgs& s, int32_t k) {
+  unsigned long long* mine = s.ring_ctr + (int64_t)(k % kRing) * kCountSlots * kCountFields;
+  for (int i = threadIdx.x; i < kCountSlots * kCountFields; i += blockDim.x) mine[i] = 0ull;
+  if (threadIdx.x == 0) {
+    s.qn[k % kRing] = 0;
+    s.seg_n[k & 1] = 0;
+  }
+}
+
 __global__ void schedule_kernel(SchedArgs s) {
-  __shared__ float x[kFeatures], h1[32], h2[32], out[kVariants];
+  __shared__ SchedShared sh;
   __shared__ int stop;
   const int t = threadIdx.x;
   const int k = s.level;
@@ -751,116 +880,31 @@ __global__ void schedule_kernel(SchedArgs s) {
         stop = 1;
       }
     }
+    for (int i = 0; i < 3; ++i) sh.sums[i] = s.sums[i];
   }
   __syncthreads();
   if (stop) return;
-  // previous level's totals (16 slots)
-  double nf = 0.0, mf = 0.0;
-  if (t == 0) {
-    const unsigned long long* c = s.ring_ctr + (int64_t)((k - 1) % kRing) * kCountSlots * kCountFields;
-    for (int q = 0; q < kCountSlots; ++q) {
-      nf += (double)c[q * kCountFields + 0];
-      mf += (double)c[q * kCountFields + 4];
-    }
-    if (k > 1) {
-      s.sums[0] += nf;
-      s.sums[1] += mf;
-    }
-    const double nu = s.n - s.sums[0], mu = s.two_m - s.sums[1];
-    const double l2n = log2(s.n > 2.0 ? s.n : 2.0), l2m = log2(1.0 + (s.two_m > 1.0 ? s.two_m : 1.0));
-    const double prev = s.sums[2];
-    double growth = log2((1.0 + nf) / (1.0 + prev)) / 8.0;
-    growth = growth > 1.0 ? 1.0 : (growth < -1.0 ? -1.0 : growth);
-    x[0] = (float)(log2(1.0 + nf) / l2n);
-    x[1] = (float)(log2(1.0 + mf) / l2m);
-    x[2] = (float)(log2(1.0 + (mu > 0.0 ? mu : 0.0)) / l2m);
-    x[3] = (float)((nu > 0.0 ? nu : 0.0) / s.n);
-    x[4] = (float)growth;
-    x[5] = (float)(log2(1.0 + s.mean_degree) / 8.0);
-    s.sums[2] = nf;
-    s.qn[k % kRing] = 0;
-    s.seg_n[k & 1] = 0;  // this level's push segment list starts empty
-    h1[0] = (float)nf;   // stash for the heuristic
-    h2[0] = (float)mf;
-    h2[1] = (float)nu;
-    h2[2] = (float)(mu > 0.0 ? mu : 0.0);
-  }
-  // clear this level's counters
-  unsigned long long* mine = s.ring_ctr + (int64_t)(k % kRing) * kCountSlots * kCountFields;
-  for (int i = t; i < kCountSlots * kCountFields; i += blockDim.x) mine[i] = 0ull;
-  __syncthreads();
-  const float hnf = h1[0], hmf = h2[0], hnu = h2[1], hmu = h2[2];
-  __syncthreads();
-  bool use_model = (s.mode == 1) && s.model;
-  if (use_model) {
-    const float* W1 = s.model;
-    const float* b1 = W1 + 32 * kFeatures;
-    const float* W2 = b1 + 32;
-    const float* b2 = W2 + 32 * 32;
-    const float* W3 = b2 + 32;
-    const float* b3 = W3 + kVariants * 32;
-    if (t < 32) {
-      float acc = b1[t];
-      for (int i = 0; i < kFeatures; ++i) acc += W1[t * kFeatures + i] * x[i];
-      h1[t] = acc > 0.f ? acc : 0.f;
-    }
-    __syncthreads();
-    if (t < 32) {
-      float acc = b2[t];
-      for (int j = 0; j < 32; ++j) acc += W2[t * 32 + j] * h1[j];
-      h2[t] = acc > 0.f ? acc : 0.f;
-    }
-    __syncthreads();
-    if (t < kVariants) {
-      float acc = b3[t];
-      for (int j = 0; j < 32; ++j) acc += W3[t * 32 + j] * h2[j];
-      out[t] = acc;
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    int32_t v;
-    if (s.mode >= 3) {
-      v = s.mode - 3;
-    } else {
-      bool finite = use_model;
-      if (use_model)
-        for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(out[i]);
-      if (finite) {
-        v = 0;
-        for (int i = 1; i < kVariants; ++i)
-          if (out[i] < out[v]) v = i;
-      } else {
-        // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
-        // pull once the frontier's edges exceed 1/14 of the unvisited edges
-        const bool pull = hmf * 14.0f > hmu;
-        (void)hnf;
-        (void)hnu;
-        v = pull ? s.heuristic_pull : kPush;
-      }
-    }
-    s.variant[k % kRing] = v;
-    if (s.log && k <= s.log_cap) {
-      float* L = s.log + (int64_t)(k - 1) * 12;
-      for (int i = 0; i < kFeatures; ++i) L[i] = x[i];
-      for (int i = 0; i < kVariants; ++i) L[kFeatures + i] = use_model ? out[i] : 0.f;
-      L[10] = (float)v;
-      L[11] = (float)k;
-    }
-  }
+  sched_clear_level(s, k);
+  schedule_pick(s, k, sh, true);
+  if (t == 0)
+    for (int i = 0; i < 3; ++i) s.sums[i] = sh.sums[i];
 }
 
 // Level-0 state of a scheduled run: the root is the frontier queue, and the
 // synthetic level-0 counters hold one discovered vertex of degree deg(root).
+// Level 1's counters, queue length and segment count start at zero too (the
+// persistent form clears one level ahead).
 __global__ void sched_init_kernel(int32_t root_row, const int32_t* deg, int32_t* q0, int32_t* qn,
-                                  unsigned long long* ring_ctr, double* sums) {
+                                  int32_t* seg_n, unsigned long long* ring_ctr, double* sums) {
   const int t = threadIdx.x;
-  for (int i = t; i < kCountSlots * kCountFields; i += blockDim.x) ring_ctr[i] = 0ull;
+  for (int i = t; i < 2 * kCountSlots * kCountFields; i += blockDim.x) ring_ctr[i] = 0ull;
   __syncthreads();
   if (t == 0) {
     const int32_t d = deg[root_row];
     q0[0] = root_row;
     qn[0] = 1;
+    qn[1] = 0;
+    seg_n[1] = 0;
     ring_ctr[0] = 1ull;
     ring_ctr[4] = (unsigned long long)d;
     sums[0] = 1.0;
@@ -868,6 +912,56 @@ __global__ void sched_init_kernel(int32_t root_row, const int32_t* deg, int32_t*
     sums[2] = 0.0;
     sums[3] = 0.0;
   }
+}
+
+// ------------------------------------------------ persistent schedule form ---
+//
+// A scheduled run in one cooperative launch.  Every workgroup computes each
+// level's variant itself from the previous level's counters (identical
+// inputs, identical arithmetic, so all take the same branch and meet the
+// same barriers); workgroup 0 records it and clears the next level's
+// counters.  A pull level is one phase; a push level is scatter, segments
+// (only when long rows were queued) and post, each closed by a grid barrier.
+
+template <class S, int U, bool STAGED>
+__global__ void persistent_sched_kernel(LevelArgs a, SchedArgs s, void* buf_a, void* buf_b,
+                                        int32_t* q0, int32_t* q1, int32_t cap, unsigned* bar,
+                                        int32_t* status, uint64_t limit) {
+  extern __shared__ uint8_t lds_stage[];
+  __shared__ SchedShared sh;
+  const bool writer = blockIdx.x == 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 3; ++i) sh.sums[i] = s.sums[i];
+  const int64_t gw = grid_wave(), nw = grid_waves();
+  const int32_t count_stats = a.count_stats;
+  for (int32_t k = 1; k <= cap; ++k) {
+    a.level = k;
+    a.vin = (k & 1) ? buf_a : buf_b;
+    a.vout = (k & 1) ? buf_b : buf_a;
+    a.q_in = (k & 1) ? q0 : q1;
+    a.q_out = (k & 1) ? q1 : q0;
+    a.seg_n = s.seg_n + (k & 1);
+    a.count_stats = count_stats && (k <= status[2]);
+    const int32_t v = schedule_pick(s, k, sh, writer);
+    if (writer && k < cap) sched_clear_level(s, k + 1);
+    if (v < kPullVariants) {
+      level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], lds_stage);
+    } else {
+      push_scatter_body<S>(a, gw, nw);
+      if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
+      if (load_count(a.seg_n) > 0) {
+        push_segments_body<S>(a, gw, nw);
+        if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
+      }
+      push_post_body<S>(a, gw, nw);
+    }
+    if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
+    if (a.any[k % kRing] != level_tag(a.run_id, k)) {
+      if (writer && threadIdx.x == 0) status[0] = k;  // levels run
+      return;
+    }
+  }
+  if (writer && threadIdx.x == 0) status[0] = -1;  // cap reached
 }
 
 // ----------------------------------------------------------- init kernel ---
@@ -989,12 +1083,6 @@ __global__ void fill_kernel(T* p, T value, int64_t count) {
 
 // --------------------------------------------------------------- launchers ---
 
-static int check_launch(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return set_error(SS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-  return SS_OK;
-}
-
 static inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)((n + threads - 1) / threads);
 }
@@ -1077,7 +1165,7 @@ int launch_push(int semiring, const LevelArgs& a, void* stream) {
   return check_launch("push kernels");
 }
 
-int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream) {
+static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id) {
   SchedArgs s;
   s.level = level;
   s.run_id = run_id;
@@ -1095,14 +1183,17 @@ int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* 
   s.heuristic_pull = p.heuristic_pull;
   s.n = p.n;
   s.two_m = p.two_m;
-  s.mean_degree = p.mean_degree;
-  schedule_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(s);
+  return s;
+}
+
+int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream) {
+  schedule_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(sched_args(p, level, run_id));
   return check_launch("schedule_kernel");
 }
 
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream) {
   sched_init_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(root_row, g.d_deg, ws.q[0],
-                                                                     ws.qn, ws.ring_ctr,
+                                                                     ws.qn, ws.seg_n, ws.ring_ctr,
                                                                      ws.sched_sums);
   return check_launch("sched_init_kernel");
 }
@@ -1114,12 +1205,22 @@ constexpr int kPersistentWaves = 16;
 
 template <class S, bool STAGED>
 static int launch_persistent_u(int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
-                               int32_t cap, unsigned* bar, int32_t* status, uint64_t limit,
-                               int64_t max_groups, hipStream_t st) {
+                               const PersistentRun& r, hipStream_t st) {
   const size_t lds = STAGED ? a.lds_bytes : 0;
-  const void* fn = unroll == 4    ? (const void*)persistent_kernel<S, 4, STAGED>
-                   : unroll == 16 ? (const void*)persistent_kernel<S, 16, STAGED>
-                                  : (const void*)persistent_kernel<S, 8, STAGED>;
+  const void* fn;
+  if (r.sched) {
+    if constexpr (S::kSingleRoot) {
+      fn = unroll == 4    ? (const void*)persistent_sched_kernel<S, 4, STAGED>
+           : unroll == 16 ? (const void*)persistent_sched_kernel<S, 16, STAGED>
+                          : (const void*)persistent_sched_kernel<S, 8, STAGED>;
+    } else {
+      return set_error(SS_EINVAL, "a scheduled run needs a single-root semiring");
+    }
+  } else {
+    fn = unroll == 4    ? (const void*)persistent_kernel<S, 4, STAGED>
+         : unroll == 16 ? (const void*)persistent_kernel<S, 16, STAGED>
+                        : (const void*)persistent_kernel<S, 8, STAGED>;
+  }
   int per_cu = 0, dev = 0, cus = 0, coop = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
@@ -1130,26 +1231,35 @@ static int launch_persistent_u(int unroll, const LevelArgs& a, void* buf_a, void
   if (!coop) return set_error(SS_EUNSUP, "the device has no cooperative launch");
   if (per_cu < 1) return set_error(SS_EUNSUP, "persistent kernel does not fit on a compute unit");
   int64_t grid = cus;
-  if (max_groups > 0 && grid > max_groups) grid = max_groups;
+  if (r.max_groups > 0 && grid > r.max_groups) grid = r.max_groups;
   LevelArgs aa = a;
-  void* args[] = {&aa, &buf_a, &buf_b, &cap, &bar, &status, &limit};
-  e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kPersistentWaves * kC), args, lds,
-                                 st);
+  int32_t cap = r.cap;
+  unsigned* bar = r.bar;
+  int32_t* status = r.status;
+  uint64_t limit = r.limit;
+  if (r.sched) {
+    SchedArgs sa = sched_args(*r.sched, 0, a.run_id);
+    int32_t* q0 = r.q0;
+    int32_t* q1 = r.q1;
+    void* args[] = {&aa, &sa, &buf_a, &buf_b, &q0, &q1, &cap, &bar, &status, &limit};
+    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kPersistentWaves * kC), args,
+                                   lds, st);
+  } else {
+    void* args[] = {&aa, &buf_a, &buf_b, &cap, &bar, &status, &limit};
+    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kPersistentWaves * kC), args,
+                                   lds, st);
+  }
   if (e != hipSuccess)
     return set_error(SS_EHIP, std::string("cooperative launch: ") + hipGetErrorString(e));
   return SS_OK;
 }
 
-int launch_persistent(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
-                      void* buf_a, void* buf_b, int32_t cap, unsigned* bar, int32_t* status,
-                      uint64_t deadline, void* stream) {
-  (void)waves;  // the persistent shape is fixed (see kPersistentWaves)
+int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
+                      const PersistentRun& r, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-#define SS_PERS(S)                                                                          \
-  return a.lds_bytes ? launch_persistent_u<S, true>(unroll, a, buf_a, buf_b, cap, bar, status, \
-                                                     deadline, max_groups, st)                \
-                     : launch_persistent_u<S, false>(unroll, a, buf_a, buf_b, cap, bar, status, \
-                                                      deadline, max_groups, st);
+#define SS_PERS(S)                                                                \
+  return a.lds_bytes ? launch_persistent_u<S, true>(unroll, a, buf_a, buf_b, r, st) \
+                     : launch_persistent_u<S, false>(unroll, a, buf_a, buf_b, r, st);
   switch (semiring) {
     case SS_TROPICAL: SS_PERS(Tropical)
     case SS_REAL: SS_PERS(Real)

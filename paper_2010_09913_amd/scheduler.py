@@ -5,9 +5,9 @@ so the state a level sees does not depend on the variants chosen before it:
 running a whole BFS with one forced variant times that variant on every level
 of that BFS, and four such runs give the full per-level timing table.  The
 features of a level are the same in all four runs.  Targets are the
-log-times of the four variants, standardised with one mean and deviation for
-all of them (so the argmin is unchanged); the MLP is trained on the GPU by the
-library's own kernels (slimsell_sched_train).
+log-times of the four variants centred per level and scaled by one deviation
+(so the argmin is unchanged and only relative costs are learned); the MLP is
+trained on the GPU by the library's own kernels (slimsell_sched_train).
 
 Usage (writes the model next to this file):
   python -m paper_2010_09913_amd.scheduler --out paper_2010_09913_amd/models/sched_selmax.npy
@@ -54,9 +54,12 @@ def collect(G: Graph, roots, semiring: str = "selmax", repeats: int = 3):
 
 
 def standardise(T):
+    """Log-times centred per level (only the variants' relative cost is
+    learned, which carries across graph sizes) and scaled by one deviation."""
     y = np.log(np.maximum(T, 1e-4))
-    mu, sd = float(y.mean()), float(y.std() + 1e-6)
-    return ((y - mu) / sd).astype(np.float32), mu, sd
+    y = y - y.mean(axis=1, keepdims=True)
+    sd = float(y.std() + 1e-6)
+    return (y / sd).astype(np.float32), 0.0, sd
 
 
 def train(X, T, steps: int = 3000, lr: float = 3e-3, seed: int = 0):
@@ -96,7 +99,7 @@ def training_graphs():
 def main() -> int:
     ap = argparse.ArgumentParser(description="train the per-level scheduler on this GPU")
     ap.add_argument("--out", default=DEFAULT_MODEL)
-    ap.add_argument("--roots", type=int, default=8, help="roots per graph")
+    ap.add_argument("--roots", type=int, default=16, help="roots per graph")
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--semiring", default="selmax")

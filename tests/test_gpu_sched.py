@@ -61,9 +61,9 @@ def _graphs():
     }
 
 
-def _run(G, root, semi, schedule):
+def _run(G, root, semi, schedule, persistent=False):
     import torch
-    res = G.bfs([root], semi, schedule=schedule, level_cap=4096)
+    res = G.bfs([root], semi, schedule=schedule, level_cap=4096, persistent=persistent)
     torch.cuda.synchronize()
     return res
 
@@ -105,11 +105,21 @@ def test_every_schedule_is_exact_and_features_match(ss, name):
                     np.testing.assert_array_equal(var, heur)
                 else:
                     assert np.all(var == ss.VARIANTS.index(mode))
+                # one cooperative launch: same results, same decisions
+                note(name, root, semi, mode, "persistent")
+                resp = _run(G, int(root), semi, mode, persistent=True)
+                _check(resp, ex, semi)
+                assert int(resp.runs["launches"][0]) == 1
+                np.testing.assert_array_equal(resp.levels["variant"][0][:it], var)
             # learned: random model -> exact; scores equal the oracle's forward
             ss.sched_load(random_model)
+            resp = _run(G, int(root), semi, "learned", persistent=True)
+            _check(resp, ex, semi)
+            logp = G.sched_log(ex.iterations)
             res = _run(G, int(root), semi, "learned")
             _check(res, ex, semi)
             log = G.sched_log(ex.iterations)
+            np.testing.assert_array_equal(logp, log)
             ref = mlp.forward(random_model, log[:, :6])
             np.testing.assert_allclose(log[:, 6:10], ref, rtol=1e-5, atol=1e-5)
             srt = np.sort(ref, axis=1)

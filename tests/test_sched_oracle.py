@@ -44,10 +44,10 @@ def test_features_by_hand_on_a_star():
     l2n, l2m = np.log2(10), np.log2(19)
     # level 1: frontier {0} (deg 9); unvisited: 9 leaves, 9 edge ends
     np.testing.assert_allclose(f[0], [np.log2(2) / l2n, np.log2(10) / l2m, np.log2(10) / l2m,
-                                      0.9, np.log2(2) / 8, np.log2(1 + 1.8) / 8])
+                                      0.9, np.log2(2) / 8, 0.0])
     # level 2: frontier = 9 leaves (deg 1 each); nothing unvisited
     np.testing.assert_allclose(f[1], [np.log2(10) / l2n, np.log2(10) / l2m, 0.0, 0.0,
-                                      np.log2(10 / 2) / 8, np.log2(1 + 1.8) / 8])
+                                      np.log2(10 / 2) / 8, np.log2(10) / 16])
     assert len(f) == 2
     h = mlp.heuristic(d, g.degree, 10, g.entries, pull_variant=1)
     assert h.tolist() == [1, 1]   # 9*14 > 9: pull; then 9*14 > 0: pull
