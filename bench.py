@@ -37,6 +37,106 @@ TEST_BYTES = {"tropical": 4, "real": 1, "boolean": 1, "selmax": 4}
 GATHER_BYTES = {"tropical": 4, "real": 4, "boolean": 1, "selmax": 4}
 
 
+PROFILE_JSON = os.path.join(ROOT, "profiles", "level_kernel_selmax_rmat_s22.json")
+PROFILE_MD = os.path.join(ROOT, "profiles", "level_kernel_selmax_rmat_s22.md")
+KERNEL_SOURCES = ["paper_2010_09913_amd/csrc/kernels.hip", "paper_2010_09913_amd/csrc/device.h",
+                  "paper_2010_09913_amd/csrc/internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel sources changed since."""
+    try:
+        with open(PROFILE_JSON) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("source_hash") != kernel_source_hash() or prof.get("kernel") != kernel:
+        return None
+    return prof.get("traffic_bytes_per_launch")
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    for name in sorted(os.listdir(d)):
+        if name.endswith(suffix):
+            return os.path.join(d, name)
+    raise FileNotFoundError(f"no *{suffix} in {d}")
+
+
+def profile_summary(args) -> int:
+    """Summarise rocprofv3 output (kernel trace, FETCH_SIZE, WRITE_SIZE of
+    the timed bench, and the same counters of a 1 GiB device copy that
+    calibrates them) into profiles/."""
+    match = "level_kernel<ss::SelMax"
+    stats = _csv_rows(_find(args.trace, "_kernel_stats.csv"))
+    row = next(r for r in stats if match in r["Name"])
+
+    def per_dispatch(d, counter, name_part):
+        rows = [r for r in _csv_rows(_find(d, "_counter_collection.csv"))
+                if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return sum(float(r["Counter_Value"]) for r in rows) / len(rows), len(rows)
+
+    fetch_kib, n_f = per_dispatch(args.fetch, "FETCH_SIZE", match)
+    write_kib, n_w = per_dispatch(args.write, "WRITE_SIZE", match)
+    copy_f, _ = per_dispatch(args.copy_fetch, "FETCH_SIZE", "copyBuffer")
+    copy_w, _ = per_dispatch(args.copy_write, "WRITE_SIZE", "copyBuffer")
+    gib_kib = float(1 << 20)                  # the copy reads and writes 1 GiB
+    f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
+    traffic = (fetch_kib * f_scale + write_kib * w_scale) * 1024.0
+    prof = {
+        "kernel": "level_kernel<selmax>", "workload": "R-MAT s22, 64 roots, sel-max, sigma=n",
+        "source_hash": kernel_source_hash(), "calls": int(row["Calls"]),
+        "avg_duration_ns": float(row["AverageNs"]), "fetch_kib_per_dispatch": fetch_kib,
+        "write_kib_per_dispatch": write_kib, "dispatches_counted": [n_f, n_w],
+        "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "traffic_bytes_per_launch": traffic,
+    }
+    out_json = os.path.join(args.out_dir, os.path.basename(PROFILE_JSON))
+    out_md = os.path.join(args.out_dir, os.path.basename(PROFILE_MD))
+    os.makedirs(args.out_dir, exist_ok=True)
+    with open(out_json, "w") as f:
+        json.dump(prof, f, indent=1)
+    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:6]
+    lines = [
+        "# level_kernel<SelMax> on R-MAT s22 (64 roots, sel-max, sigma = n)", "",
+        "Commands (run from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+        f"    {args.cmd_trace}", f"    {args.cmd_fetch}", f"    {args.cmd_write}",
+        f"    {args.cmd_copy_fetch}", f"    {args.cmd_copy_write}", "",
+        "Kernel trace (`--kernel-trace --stats`), top kernels by total time:", "",
+        "| Kernel | Calls | Average ns | Min ns | Max ns | % |", "|---|---|---|---|---|---|"]
+    for r in top:
+        lines.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{r['MinNs']} | {r['MaxNs']} | {float(r['Percentage']):.1f} |")
+    lines += ["", "HBM counters per dispatch of the level kernel (KiB), and the copy probe "
+              "(1 GiB read + 1 GiB written per dispatch) that calibrates them:", "",
+              "| | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
+              f"| level kernel, per dispatch | {fetch_kib:.0f} | {write_kib:.0f} |",
+              f"| copy probe, per dispatch | {copy_f:.0f} | {copy_w:.0f} |",
+              f"| scale (1 GiB / copy reading) | {f_scale:.3f} | {w_scale:.3f} |", "",
+              f"Traffic per launch: {traffic / 1e6:.1f} MB (scaled fetch + write).  "
+              f"Kernel sources hash {prof['source_hash']}.", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    print(json.dumps(prof))
+    return 0
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -79,20 +179,26 @@ def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=Tru
     t0 = time.perf_counter()
     runs = []
     for _ in range(steps):
-        r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule,
+        r = G.bfs(roots, semi, split_len=split, timing="bfs", schedule=schedule,
                   persistent=persistent)
         runs.append(r.runs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out.update(wall=wall, runs=runs)
+    # one more step, untimed, with events around every level launch (the
+    # per-launch kernel time of the roofline)
+    r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule,
+              persistent=persistent)
+    torch.cuda.synchronize()
+    out["kernel_runs"] = r.runs
     return out
 
 
 def summarise(out, roots, semi, n, nonempty_chunks, steps):
     m_cc = out["m_cc"].astype(np.float64)
     bfs_ms = np.stack([r["bfs_ms"] for r in out["runs"]])        # [steps, roots]
-    kern_ms = np.stack([r["kernel_ms"] for r in out["runs"]])
-    launches = np.stack([r["launches"] for r in out["runs"]])
+    kern_ms = out["kernel_runs"]["kernel_ms"]                      # [roots], one step
+    launches = out["kernel_runs"]["launches"]
     teps = m_cc[None, :] / (bfs_ms * 1e-3)
     hmean = teps.size / np.sum(1.0 / teps) / 1e9
     whole = m_cc.sum() * steps / out["wall"] / 1e9
@@ -105,8 +211,8 @@ def summarise(out, roots, semi, n, nonempty_chunks, steps):
                                                nonempty_chunks) for i in range(len(roots))])
         bytes_per_step = per_root.sum()
         kernel_s = kern_ms.sum() / 1e3
-        achieved = bytes_per_step * steps / kernel_s / 1e9
-        s.update(bytes_per_launch=float(bytes_per_step * steps / launches.sum()),
+        achieved = bytes_per_step / kernel_s / 1e9
+        s.update(bytes_per_launch=float(bytes_per_step / launches.sum()),
                  achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
                  cells_per_bfs=float(np.mean([out["levels"]["active_cells"][i][:iters[i]].sum()
                                               for i in range(len(roots))])))
@@ -126,6 +232,48 @@ def _events_ms(torch, fn, reps=3):
     return float(np.median(out))
 
 
+def storage_report(ss, e, sigmas) -> dict:
+    """Words (4 B) of each representation of Table "sizes", from the built
+    SlimSell layout (E directed entries, P padding cells, n_c chunks):
+    SlimSell col + cs + cl = E + P + 2 n_c; Sell-C-sigma pads val as well as col,
+    2(E + P) + 2 n_c; CSR val + col + row = 2E + n; AL = E + n."""
+    out = {}
+    for sg in sigmas:
+        L = ss.layout_build(e.src, e.dst, e.n, sigma=sg, arrays=False)
+        E, P, nc, n = L.entries, L.cells - L.entries, L.n_chunks, e.n
+        slim, sell = E + P + 2 * nc, 2 * (E + P) + 2 * nc
+        out["n" if sg == 0 else str(sg)] = {
+            "padding": int(P), "slimsell": int(slim), "sell_c_sigma": int(sell),
+            "csr": int(2 * E + n), "al": int(E + n),
+            "slimsell_vs_sell": round(slim / sell, 4), "slimsell_vs_al": round(slim / (E + n), 4)}
+    return out
+
+
+def bench_sell(ss, e, roots, torch) -> dict:
+    """Speedup of SlimSell over Sell-C-sigma (val streamed beside col), per
+    semiring, for a small and a large sorting scope (Table "slimsell")."""
+    out = {}
+    for sg in (1, 1 << 18):
+        G = ss.Graph.from_edgelist(e, sigma=sg)
+        row = {}
+        for semi in ("boolean", "real", "tropical", "selmax"):
+            t = {}
+            for sell in (False, True):
+                G.bfs(roots, semi, sell=sell)
+                tot = 0.0
+                for _ in range(2):
+                    r = G.bfs(roots, semi, sell=sell, timing="bfs")
+                    tot += float(r.runs["bfs_ms"].sum())
+                torch.cuda.synchronize()
+                t[sell] = tot / (2 * len(roots))
+            row[semi] = {"slimsell_ms": round(t[False], 4), "sell_ms": round(t[True], 4),
+                         "speedup": round(t[True] / t[False], 3)}
+            log(f"sell sigma={sg} {semi}: {row[semi]}")
+        G.close()
+        out[f"sigma_{sg}"] = row
+    return out
+
+
 def bench_dp(G, roots, torch) -> dict:
     """Mean BFS time per root without and with parents: sel-max yields them from
     the product, the other semirings by the DP transformation after the BFS
@@ -138,7 +286,7 @@ def bench_dp(G, roots, torch) -> dict:
             G.bfs(roots, semi, **kw)
             tot = 0.0
             for _ in range(2):
-                r = G.bfs(roots, semi, timing=True, **kw)
+                r = G.bfs(roots, semi, timing="bfs", **kw)
                 tot += float(r.runs["bfs_ms"].sum())
             torch.cuda.synchronize()
             row["dp_ms" if dp else "no_dp_ms"] = round(tot / (2 * len(roots)), 4)
@@ -224,7 +372,7 @@ def bench_learned(ss, graphgen, torch) -> dict:
             G.bfs([int(rr[0])], "selmax", schedule=sched, persistent=pers)
             tot = 0.0
             for r in rr:
-                x = G.bfs([int(r)], "selmax", schedule=sched, timing=True, persistent=pers)
+                x = G.bfs([int(r)], "selmax", schedule=sched, timing="bfs", persistent=pers)
                 tot += float(x.runs["bfs_ms"][0])
             res[mode] = round(tot / len(rr), 3)
             log(f"{name} {mode}: {tot / len(rr):.2f} ms per BFS")
@@ -257,7 +405,16 @@ def main() -> int:
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-schedule comparison (R-MAT s24, 4096^2 grid)")
+    ap.add_argument("--profile-summary", action="store_true",
+                    help="summarise rocprofv3 output into profiles/ (no GPU needed)")
+    for name in ("trace", "fetch", "write", "copy-fetch", "copy-write"):
+        ap.add_argument("--" + name, help="rocprofv3 output directory")
+        ap.add_argument("--cmd-" + name, default="", help="the command that produced it")
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"),
+                    help="where --profile-summary writes")
     args = ap.parse_args()
+    if args.profile_summary:
+        return profile_summary(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -331,7 +488,8 @@ def main() -> int:
     if "achieved_gbs" in s:
         result["roofline"] = {
             "bound": "hbm", "achieved": round(s["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(s["frac"], 4), "traffic": None,
+            "unit": "GB/s", "frac": round(s["frac"], 4),
+            "traffic": measured_traffic(f"level_kernel<{semi}>"),
             "kernel": f"level_kernel<{semi}>",
             "bytes_per_launch": round(s["bytes_per_launch"]),
             "mean_launch_ms": round(s["mean_launch_ms"], 5),
@@ -379,6 +537,8 @@ def main() -> int:
         result["split_sweep"] = sweep
         result["dp"] = bench_dp(G, roots[:16], torch)
         G.close()
+        result["slimsell_vs_sell"] = bench_sell(ss, e, roots[:8], torch)
+        result["storage_words"] = {"rmat_s22": storage_report(ss, e, (1, 64, 2048, 1 << 14, 0))}
         # Erdos-Renyi graph of the same size (mean degree 32)
         er = graphgen.er(1 << args.scale, 16 << args.scale, seed=2)
         er_roots = graphgen.pick_roots(er, args.roots, seed=1003)
@@ -388,6 +548,7 @@ def main() -> int:
         oe = run_workload(ss, Ge, er_roots, semi, args.split, max(1, args.steps // 2), 1, deg_e)
         se = summarise(oe, er_roots, semi, er.n, ne, max(1, args.steps // 2))
         log(f"er: {se}")
+        result["storage_words"]["er_2^22"] = storage_report(ss, er, (1, 2048, 0))
         result["er_2^22_deg32"] = {"gteps": round(se["gteps_wall"], 4),
                                    "gteps_hmean": round(se["gteps_hmean"], 4),
                                    "frac": round(se.get("frac", 0.0), 4)}

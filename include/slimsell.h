@@ -250,6 +250,9 @@ typedef struct {
 
 #define SS_STATS_TIME 1     /* hipEvents around every level kernel and every BFS */
 #define SS_STATS_COUNTERS 2 /* fused per-level counters (a few atomics per wavefront) */
+/* hipEvents around every BFS only (bfs_ms; kernel_ms and per-level ms stay 0):
+ * no per-level host work, for runs with thousands of levels */
+#define SS_STATS_TIME_BFS 16
 /* Run all levels of a BFS in one cooperative (persistent) kernel launch with a
  * device-wide barrier between levels, instead of one launch per level: one
  * 1024-thread workgroup per compute unit (capped by the graph's max_groups).
@@ -259,6 +262,12 @@ typedef struct {
  * those of the launch-per-level form.  Per-level times are not available in
  * this mode; a barrier that waits more than 5 s is reported as SS_EHIP. */
 #define SS_RUN_PERSISTENT 4
+/* Comparator: run the levels on Sell-C-sigma instead of SlimSell (Section
+ * II-C, Table "sizes"): a val array (1 = edge, 0 = padding) is streamed beside
+ * a col array whose padding cells hold a valid row, so each cell costs 8 bytes
+ * instead of 4.  Built on the device at first use (2 x 4 B per cell).  Same
+ * results; single-root levels only (no schedule, no persistent launch). */
+#define SS_SELL_VAL 8
 
 /*
  * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
@@ -291,7 +300,8 @@ typedef struct {
  *   stream          : hipStream_t.
  *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
  *                     (eccentricity + 1; the last one discovers nothing).
- *   flags           : SS_STATS_TIME, SS_STATS_COUNTERS, SS_RUN_PERSISTENT.
+ *   flags           : SS_STATS_TIME, SS_STATS_TIME_BFS, SS_STATS_COUNTERS,
+ *                     SS_RUN_PERSISTENT, SS_SELL_VAL.
  *   level_cap       : levels per root recorded in level_stats_out.
  *   level_stats_out : host ss_level_stats[num_roots * level_cap] or NULL;
  *                     entry [r * level_cap + k - 1] describes level k of root r.

@@ -65,8 +65,10 @@ class Layout:
         return self.cells - self.entries
 
 
-def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
-    """Build the SlimSell layout on the host and copy it out (no device needed)."""
+def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK,
+                 arrays: bool = True) -> Layout:
+    """Build the SlimSell layout on the host and copy it out (no device needed);
+    arrays=False returns the sizes only (empty arrays)."""
     lib = _native.load()
     src = _i32(src)
     dst = _i32(dst)
@@ -78,7 +80,7 @@ def layout_build(src, dst, n: int, sigma: int = 0, C: int = CHUNK) -> Layout:
         check(lib.slimsell_layout_view(h, ctypes.byref(v)))
 
         def arr(ptr, count, dt):
-            if count == 0:
+            if count == 0 or not arrays:
                 return np.zeros(0, dt)
             return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
 
@@ -215,13 +217,16 @@ class Graph:
             waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
             level_cap: int = 0, timing: bool = False, counters: bool = None,
             persistent: bool = False, want_parent: bool = True, want_real: bool = True,
-            dp: bool = False, dist=None, parent=None, real_val=None) -> BfsResult:
+            dp: bool = False, sell: bool = False, dist=None, parent=None,
+            real_val=None) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
         Sel-max returns parents (unless want_parent=False); dp=True gives the
         other semirings parents too, by the DP transformation after each BFS.
+        sell=True runs the Sell-C-sigma comparator (a val array beside col).
         level_cap > 0 records per-level statistics (fused counters unless
-        counters=False); timing=True adds event timings per level and per root.
+        counters=False); timing=True adds event timings per level and per root,
+        timing="bfs" per root only.
         """
         import torch
         s = _semiring(semiring)
@@ -251,9 +256,11 @@ class Graph:
         o.iterations_out = iters.ctypes.data_as(_native.c_i32p)
         if counters is None:
             counters = level_cap > 0
-        o.flags = (_native.SS_STATS_TIME if timing else 0) | (
+        o.flags = (_native.SS_STATS_TIME_BFS if timing == "bfs" else
+                   _native.SS_STATS_TIME if timing else 0) | (
             _native.SS_STATS_COUNTERS if counters else 0) | (
-            _native.SS_RUN_PERSISTENT if persistent else 0)
+            _native.SS_RUN_PERSISTENT if persistent else 0) | (
+            _native.SS_SELL_VAL if sell else 0)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * (nr * level_cap))()

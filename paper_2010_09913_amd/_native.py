@@ -83,6 +83,8 @@ class AutotuneResult(ctypes.Structure):
 SS_STATS_TIME = 1
 SS_STATS_COUNTERS = 2
 SS_RUN_PERSISTENT = 4
+SS_SELL_VAL = 8
+SS_STATS_TIME_BFS = 16
 
 
 class BfsOpts(ctypes.Structure):

@@ -75,6 +75,7 @@ static void release_graph(Graph* g) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(g->device);
   void* ptrs[] = {g->d_col,     g->d_cs,   g->d_cl,    g->d_v,     g->d_perm, g->d_deg,
+                  g->d_scol,    g->d_sval,
                   g->ws.vec_a,  g->ws.vec_b, g->ws.state, g->ws.g, g->ws.d,
                   g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters,
                   g->d_voff,    g->bw.vis, g->bw.fa,   g->bw.fb,   g->bw.acc64,
@@ -200,7 +201,7 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.qn, kRing))) return rc;
   if ((rc = dalloc(&ws.variant, kRing))) return rc;
   if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kCountSlots * kCountFields))) return rc;
-  if ((rc = dalloc(&ws.sched_sums, 4))) return rc;
+  if ((rc = dalloc(&ws.sched_sums, 8))) return rc;
   if ((rc = dalloc(&ws.model, kModelSize))) return rc;
   ws.sched_log_cap = std::min<int64_t>((int64_t)g.n + 2, 65536);
   if ((rc = dalloc(&ws.sched_log, ws.sched_log_cap * 12))) return rc;
@@ -272,7 +273,8 @@ uint32_t next_run_id(Graph& g) {
 struct RunPlan {
   int waves = 4, unroll = 8;
   int64_t max_groups = 0, cap = 0, lcap = 0, words_per_run = 0;
-  bool timing = false, counting = false, persistent = false;
+  bool timing = false, counting = false, persistent = false, sell = false;
+  bool level_events = false;  // timing: events around every level launch too
   int32_t slimwork = 2;
   int32_t schedule = 0;
   uint32_t lds_bytes = 0;
@@ -305,9 +307,20 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   p->max_groups = g.tune.max_groups;
   p->cap = (o->max_levels > 0) ? std::min<int64_t>(o->max_levels, default_cap) : default_cap;
   if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
-  if (o->flags & ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT))
+  if (o->flags &
+      ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT | SS_SELL_VAL | SS_STATS_TIME_BFS))
     return set_error(SS_EINVAL, "bad flags");
   p->persistent = (o->flags & SS_RUN_PERSISTENT) != 0;
+  p->sell = (o->flags & SS_SELL_VAL) != 0;
+  if (p->sell && (p->persistent || o->schedule || policy == kBatchSemiring))
+    return set_error(SS_EINVAL, "SS_SELL_VAL runs plain single-root levels only");
+  if (p->sell && !g.d_scol) {
+    // Sell-C-sigma arrays, built once per graph
+    SS_HIP(hipMalloc(&g.d_scol, sizeof(int32_t) * std::max<int64_t>(g.cells, 1)));
+    SS_HIP(hipMalloc(&g.d_sval, sizeof(int32_t) * std::max<int64_t>(g.cells, 1)));
+    int brc = launch_sell_build(g.d_col, g.cells, g.d_scol, g.d_sval, st);
+    if (brc) return brc;
+  }
   p->slimwork = o->slimwork;
   p->lds_bytes = 0;
   if (g.tune.lds_kib > 0) {
@@ -336,7 +349,8 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
       g.ws.model_version = version;
     }
   }
-  p->timing = (o->flags & SS_STATS_TIME) != 0;
+  p->timing = (o->flags & (SS_STATS_TIME | SS_STATS_TIME_BFS)) != 0;
+  p->level_events = (o->flags & SS_STATS_TIME) && !(o->flags & SS_STATS_TIME_BFS);
   p->lcap = o->level_cap;
   p->counting = (o->flags & SS_STATS_COUNTERS) && p->lcap > 0 && o->level_stats_out;
   p->words_per_run = (p->lcap + 1) * kCountSlots * kCountFields;
@@ -364,7 +378,8 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
                            int32_t run_idx) {
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.col = g.d_col;
+  a.col = p.sell ? g.d_scol : g.d_col;
+  a.val = p.sell ? g.d_sval : nullptr;
   a.cs = g.d_cs;
   a.cl = g.d_cl;
   a.v = g.d_v;
@@ -393,11 +408,23 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
       a.vn_units[v] = p.vul[v]->count;
     }
     a.qn = g.ws.qn;
-    a.want_queue = 1;
     a.ring_ctr = g.ws.ring_ctr;
+    a.segs = g.ws.segs;
+    a.seg_n = g.ws.seg_n;
   }
   (void)o;
   return a;
+}
+
+// A scheduled run writes frontier queues, queue lengths, push segments and
+// ring counters: refuse to launch one with any of them missing.
+static int check_sched_args(const LevelArgs& a) {
+  if (!a.variant || !a.qn || !a.ring_ctr || !a.segs || !a.seg_n)
+    return set_error(SS_EHIP, "internal: scheduled run without its queue buffers");
+  for (int v = 0; v < kPullVariants; ++v)
+    if (!a.vunits[v] || !a.vpieces[v])
+      return set_error(SS_EHIP, "internal: scheduled run without its work units");
+  return SS_OK;
 }
 
 // The level loop of one BFS run: level kernels are enqueued kLookahead ahead
@@ -438,12 +465,15 @@ static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, v
   const uint64_t limit = (uint64_t)rate_khz * 1000ull * 5ull;  // 5 s per barrier wait
   a.count_stats = p.counting ? 1 : 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (p.timing) {
+  if (p.level_events) {
     if ((rc = pool_event(g, log->next_ev++, &e0))) return rc;
     if ((rc = pool_event(g, log->next_ev++, &e1))) return rc;
     SS_HIP(hipEventRecord(e0, st));
   }
+  if (p.schedule && (rc = check_sched_args(a))) return rc;
   const SchedLaunch sl = sched_launch(g, p);
+  if (p.schedule && (!sl.sums || !sl.seg_n || !g.ws.q[0] || !g.ws.q[1]))
+    return set_error(SS_EHIP, "internal: scheduled run without its queue buffers");
   PersistentRun pr;
   pr.cap = (int32_t)std::min<int64_t>(p.cap, INT32_MAX);
   pr.max_groups = p.max_groups;
@@ -455,7 +485,7 @@ static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, v
   pr.q1 = g.ws.q[1];
   rc = launch_persistent(policy, p.unroll, a, buf_a, buf_b, pr, st);
   if (rc) return rc;
-  if (p.timing) SS_HIP(hipEventRecord(e1, st));
+  if (p.level_events) SS_HIP(hipEventRecord(e1, st));
   int32_t status[4] = {0, 0, 0, 0};
   SS_HIP(hipMemcpyAsync(status, g.ws.pstatus, sizeof(status), hipMemcpyDeviceToHost, st));
   SS_HIP(hipStreamSynchronize(st));
@@ -472,6 +502,10 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
   constexpr int kLookahead = 2;
   int32_t launched = 0;
   const SchedLaunch sl = sched_launch(g, p);
+  if (p.schedule) {
+    int rc = check_sched_args(a);
+    if (rc) return rc;
+  }
   auto launch = [&](int32_t k) -> int {
     a.level = k;
     a.vin = (k & 1) ? buf_a : buf_b;
@@ -482,7 +516,7 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
     a.seg_n = g.ws.seg_n + (k & 1);
     a.count_stats = (p.counting && k <= p.lcap) ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p.timing) {
+    if (p.level_events) {
       int pr;
       if ((pr = pool_event(g, log->next_ev++, &e0))) return pr;
       if ((pr = pool_event(g, log->next_ev++, &e1))) return pr;
@@ -490,17 +524,17 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
     }
     int lr;
     if (p.schedule) {
-      if ((lr = launch_schedule(sl, k, a.run_id, st))) return lr;
       LevelArgs pa = a;
       int64_t most = 0;
       for (int v = 0; v < kPullVariants; ++v) most = std::max(most, pa.vn_units[v]);
       pa.n_units = most;  // grid size only: the kernel uses its variant's units
-      if ((lr = launch_level(policy, p.waves, p.unroll, p.max_groups, pa, st))) return lr;
+      if ((lr = launch_sched_level(policy, p.waves, p.unroll, p.max_groups, pa, sl, st)))
+        return lr;
       if ((lr = launch_push(policy, a, st))) return lr;
     } else {
       if ((lr = launch_level(policy, p.waves, p.unroll, p.max_groups, a, st))) return lr;
     }
-    if (p.timing) SS_HIP(hipEventRecord(e1, st));
+    if (p.level_events) SS_HIP(hipEventRecord(e1, st));
     return SS_OK;
   };
   for (int32_t j = 1;; ++j) {
@@ -548,7 +582,10 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
   for (int32_t r = 0; r < runs; ++r) {
     float kernel_ms = 0.f, bfs_ms = 0.f;
     std::vector<float> lvl_ms((size_t)log.launches[r], 0.f);
-    if (p.timing) {
+    if (p.timing && !p.level_events) {
+      const size_t e = log.ev_first[r];
+      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1)));
+    } else if (p.timing) {
       const size_t e = log.ev_first[r];
       for (int32_t k = 0; k < log.launches[r]; ++k) {
         float ms = 0.f;
@@ -571,7 +608,7 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
         ss_level_stats& ls = o->level_stats_out[r * p.lcap + (k - 1)];
         std::memset(&ls, 0, sizeof(ls));
         if (k > log.iters[r]) continue;
-        ls.ms = (p.timing && k - 1 < (int64_t)lvl_ms.size()) ? lvl_ms[k - 1] : 0.f;
+        ls.ms = (p.level_events && k - 1 < (int64_t)lvl_ms.size()) ? lvl_ms[k - 1] : 0.f;
         ls.variant = -1;
         if (p.schedule && k <= (int64_t)hlog.size() / 12) ls.variant = (int32_t)hlog[(k - 1) * 12 + 10];
         if (p.counting) {

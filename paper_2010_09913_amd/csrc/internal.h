@@ -81,7 +81,7 @@ struct Workspace {
   int32_t* qn = nullptr;               // [kRing] queue length per level
   int32_t* variant = nullptr;          // [kRing] chosen variant per level
   unsigned long long* ring_ctr = nullptr;  // [kRing * kCountSlots * kCountFields]
-  double* sched_sums = nullptr;        // [4] running totals for the features
+  double* sched_sums = nullptr;        // [8] running totals for the features, 2 buffers
   float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
   int64_t sched_log_cap = 0;
   float* model = nullptr;              // [kModelSize] device copy of the scheduler model
@@ -135,6 +135,10 @@ struct Graph {
   int32_t* d_v = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_deg = nullptr;     // degree of each row (row order)
+  // Sell-C-sigma comparator (built on first use): col with padding cells
+  // holding row 0 and the val array (1 = edge, 0 = padding)
+  int32_t* d_scol = nullptr;
+  int32_t* d_sval = nullptr;
   std::vector<int32_t> h_perm;  // row of each original vertex
   std::vector<int32_t> h_cl;    // chunk lengths (for unit decomposition)
   std::vector<int32_t> h_degree;  // degree of each original vertex
@@ -156,6 +160,7 @@ struct Graph {
 // Arguments of one level kernel.
 struct LevelArgs {
   const int32_t* col;
+  const int32_t* val;  // Sell-C-sigma comparator: val beside col (nullptr = SlimSell)
   const int64_t* cs;
   const int32_t* cl;
   const int32_t* v;
@@ -183,10 +188,9 @@ struct LevelArgs {
   const int32_t* q_in;   // frontier rows of the previous level
   int32_t* q_out;        // frontier rows of this level
   int32_t* qn;           // [kRing] queue lengths
-  int32_t want_queue;
   unsigned long long* ring_ctr;  // per-level counters for the schedule (ring)
   int2* segs;            // push: segments (row, first cell) of long frontier rows
-  int32_t* seg_n;        // push: segment count of this level (cleared by the schedule kernel)
+  int32_t* seg_n;        // push: segment count of this level (cleared one level ahead)
   // batched SpMM only
   unsigned long long* acc64;
   unsigned long long* vis;
@@ -200,7 +204,7 @@ struct LevelArgs {
   int32_t count_stats;
 };
 
-// Parameters of the schedule kernel that stay fixed over one run.
+// Parameters of the schedule that stay fixed over one run.
 struct SchedLaunch {
   uint64_t* any;
   uint64_t* report;
@@ -236,7 +240,10 @@ struct PersistentRun {
 int launch_push(int semiring, const LevelArgs& a, void* stream);
 int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
                       const PersistentRun& r, void* stream);
-int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream);
+// One scheduled level: variant choice, then the pull variant or the push
+// scatter (launch_push adds the push segments and post kernels).
+int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
+                       const LevelArgs& a, const SchedLaunch& p, void* stream);
 // DP transformation (dp.hip): parents (original IDs) from distances (original
 // IDs) of one root, through the workspace's d, g and acc buffers.
 int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t max_groups,
@@ -248,6 +255,9 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
 int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,
                     int32_t* parent, float* real_val, void* stream);
 int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream);
+// Sell-C-sigma arrays from the SlimSell col (same shape).
+int launch_sell_build(const int32_t* col, int64_t cells, int32_t* scol, int32_t* sval,
+                      void* stream);
 int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, void* stream);
 int launch_batch_finalise(const Graph& g, const BatchWorkspace& b, int32_t rpg, int32_t* dist,
                           void* stream);

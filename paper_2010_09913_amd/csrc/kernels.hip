@@ -118,6 +118,10 @@ struct Tropical {
     return atomicMin(&a.acc[w], v) == kInf;
   }
   __device__ static void publish_one(const LevelArgs&, int32_t) {}
+  // the row entered the frontier at `level` (its distance)
+  __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
+    return a.state[row] == level;
+  }
   // f_k^row = min(f_{k-1}^row, acc): the zero diagonal of A' keeps the old value
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const int32_t own = a.state[row];
@@ -160,6 +164,9 @@ struct Real {
     return atomicAdd(reinterpret_cast<float*>(&a.acc[w]), v) == 0.0f;
   }
   __device__ static void publish_one(const LevelArgs&, int32_t) {}
+  __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
+    return a.d[row] == level;
+  }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const uint8_t gg = a.g[row];
     const bool fresh = (acc * (float)gg) != 0.0f;
@@ -203,6 +210,9 @@ struct Boolean {
     return atomicOr(reinterpret_cast<uint32_t*>(&a.acc[w]), v) == 0u;
   }
   __device__ static void publish_one(const LevelArgs&, int32_t) {}
+  __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
+    return a.d[row] == level;
+  }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (acc != 0u) && (a.g[row] != 0);
     static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
@@ -261,6 +271,9 @@ struct SelMax {
   // a row entering the frontier in a push level sets its bit in the word
   __device__ static void publish_one(const LevelArgs& a, int32_t row) {
     atomicOr(static_cast<unsigned long long*>(a.vout) + (row >> 6), 1ull << (row & 63));
+  }
+  __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
+    return a.d[row] == level;
   }
   __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
     const bool fresh = (a.state[row] == 0) && (acc != 0);
@@ -325,22 +338,39 @@ struct Batch {
 // Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
 // U independent streaming loads of `col`, then the U gathers of the block.  A
 // lane that is off (its row is final) issues no loads at all.
-template <class S, int U, bool STAGED>
+//
+// VAL (the Sell-C-sigma comparator of Section II-C): a second stream, val,
+// runs beside col and decides whether a cell is an edge (1) or padding (0);
+// the padding cells of that col hold a valid row, so only val marks them.
+template <class S, int U, bool STAGED, bool VAL = false>
 __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Stage st,
                                                  const int32_t* __restrict__ p, int32_t ncols,
                                                  bool on) {
   typename S::Acc acc = S::identity();
   if (!on) return acc;
+  const int32_t* __restrict__ pv = VAL ? a.val + (p - a.col) : nullptr;
   int32_t j = 0;
   for (; j + U <= ncols; j += U) {
     int32_t c[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+    if (VAL) {
+      int32_t w[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) w[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+#pragma unroll
+      for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+      pv += (int64_t)U * kC;
+    }
     acc = S::template block<U, STAGED>(a, r, st, c, acc);
     p += (int64_t)U * kC;
   }
   for (; j < ncols; ++j) {
     int32_t c[1] = {__builtin_nontemporal_load(p)};
+    if (VAL) {
+      c[0] = __builtin_nontemporal_load(pv) ? c[0] : -1;
+      pv += kC;
+    }
     acc = S::template block<1, STAGED>(a, r, st, c, acc);
     p += kC;
   }
@@ -348,19 +378,6 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
 }
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
-
-// Append this lane's row to the level's frontier queue when `fresh`; one
-// atomic per wavefront.
-__device__ __forceinline__ void queue_append(const LevelArgs& a, bool fresh, int32_t row,
-                                             int lane) {
-  const uint64_t m = __ballot(fresh);
-  if (!m) return;
-  const int leader = __ffsll((long long)m) - 1;
-  int32_t base = 0;
-  if (lane == leader) base = atomicAdd(&a.qn[a.level % kRing], (int32_t)__popcll(m));
-  base = __shfl(base, leader);
-  if (fresh) a.q_out[base + __popcll(m & lanes_below(lane))] = row;
-}
 
 // Post-process the rows of one chunk; returns how many entered the frontier
 // and adds their degrees to `fdeg`.
@@ -371,7 +388,6 @@ __device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chun
   const uint64_t mask = __ballot(fresh);
   S::publish(a, chunk, mask, lane);
   if (fresh) fdeg += (uint64_t)a.deg[row];
-  if (a.want_queue) queue_append(a, fresh, row, lane);
   return (uint32_t)__popcll(mask);
 }
 
@@ -411,7 +427,7 @@ __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uin
 // stops at the longest row that is still live.
 // The work of one level for one workgroup: stage the LDS prefix, sweep the
 // work units assigned to this workgroup's wavefronts, post-process, count.
-template <class S, int U, bool STAGED>
+template <class S, int U, bool STAGED, bool VAL = false>
 __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units,
                                            const int32_t* pieces, int64_t n_units,
                                            uint8_t* lds_stage) {
@@ -457,7 +473,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       const int32_t ncols = hi > j0 ? hi - j0 : 0;
       n_cols += (uint64_t)ncols;
       const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
-      typename S::Acc acc = sweep<S, U, STAGED>(a, rs, st, p, ncols, on);
+      typename S::Acc acc = sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on);
       const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
         found += finish_rows<S>(a, c, row, acc, lane, fdeg);
@@ -484,22 +500,11 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
 }
 
 
-template <class S, int U, bool STAGED>
+template <class S, int U, bool STAGED, bool VAL = false>
 __global__ void level_kernel(LevelArgs a) {
   extern __shared__ uint8_t lds_stage[];
 
-  const Unit* units = a.units;
-  const int32_t* pieces = a.pieces;
-  int64_t n_units = a.n_units;
-  if (a.variant) {
-    // scheduled level: the schedule kernel has reported the previous level
-    // and chosen this level's variant; only the pull variants run here
-    const int32_t vs = a.variant[a.level % kRing];
-    if (vs < 0 || vs >= kPullVariants) return;
-    units = a.vunits[vs];
-    pieces = a.vpieces[vs];
-    n_units = a.vn_units[vs];
-  } else if (a.level > 1) {
+  if (a.level > 1) {
     // Stop if the previous level discovered nothing, and tell the host what
     // the previous level found (one thread of the first workgroup).
     const uint64_t want = level_tag(a.run_id, a.level - 1);
@@ -511,7 +516,7 @@ __global__ void level_kernel(LevelArgs a) {
     if (!prev_found) return;
   }
 
-  level_body<S, U, STAGED>(a, units, pieces, n_units, lds_stage);
+  level_body<S, U, STAGED, VAL>(a, a.units, a.pieces, a.n_units, lds_stage);
 }
 
 // ------------------------------------------------------- persistent form ---
@@ -608,14 +613,25 @@ __device__ __forceinline__ int32_t load_count(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The frontier rows of level k-1 come from the queue the push post of level
+// k-1 (or the scheduled run's init) filled, or, after a pull level, which
+// keeps no queue, from a scan of the rows that entered at level k-1.
 template <class S>
 __device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw, int64_t nw) {
   const int lane = threadIdx.x & (kC - 1);
-  const int32_t nq = load_count(&a.qn[(a.level - 1) % kRing]);
+  const bool scan = a.level > 1 && a.variant[(a.level - 1) % kRing] < kPullVariants &&
+                    a.variant[(a.level - 1) % kRing] >= 0;
+  const int64_t nq = scan ? (int64_t)a.n_pad : (int64_t)load_count(&a.qn[(a.level - 1) % kRing]);
   uint64_t cells = 0;
   for (int64_t base = gw * kC; base < nq; base += nw * kC) {
     const int64_t i = base + lane;
-    const int32_t u = i < nq ? a.q_in[i] : -1;
+    int32_t u = -1;
+    if (i < nq) {
+      if (!scan)
+        u = a.q_in[i];
+      else if (S::entered(a, (int32_t)i, a.level - 1))
+        u = (int32_t)i;
+    }
     const int32_t du = u >= 0 ? a.deg[u] : 0;
     const bool big = du > kPushLaneMax;
     if (u >= 0 && !big) {
@@ -695,14 +711,8 @@ __device__ __forceinline__ int64_t grid_wave() {
 }
 __device__ __forceinline__ int64_t grid_waves() { return ((int64_t)gridDim.x * blockDim.x) / kC; }
 
-// Launched after the pull kernel of every scheduled level; they return at
-// once unless the level's variant is push.
-template <class S>
-__global__ void push_scatter_kernel(LevelArgs a) {
-  if (a.variant[a.level % kRing] != kPush) return;
-  push_scatter_body<S>(a, grid_wave(), grid_waves());
-}
-
+// Launched after the level kernel of every scheduled level (which runs the
+// push scatter itself); they return at once unless the variant is push.
 template <class S>
 __global__ void push_segments_kernel(LevelArgs a) {
   if (a.variant[a.level % kRing] != kPush) return;
@@ -717,13 +727,13 @@ __global__ void push_post_kernel(LevelArgs a) {
 
 // -------------------------------------------------------------- schedule ---
 //
-// Runs before every scheduled level k: reports level k-1 to the host, stops
-// the run if it found nothing, clears level k's counters and queue, updates
-// the running totals and picks level k's variant from six features of the
-// frontier: by the MLP (6 -> 32 -> 32 -> 4, ReLU; smallest predicted
-// log-time wins) when a model is loaded and gives finite scores, else by the
-// fixed heuristic (pull once the frontier's edges exceed 1/14 of the
-// unvisited edges, otherwise push).
+// At the start of every scheduled level k each workgroup stops the run if
+// level k-1 found nothing, else updates the running totals and picks level
+// k's variant from six features of the frontier: by the MLP (6 -> 32 -> 32 ->
+// 4, ReLU; smallest predicted log-time wins) when a model is loaded and gives
+// finite scores, else by the fixed heuristic (pull once the frontier's edges
+// exceed 1/14 of the unvisited edges, otherwise push).  The counters, queue
+// length and segment count of a level are cleared one level ahead.
 struct SchedArgs {
   int32_t level;
   uint32_t run_id;
@@ -749,7 +759,7 @@ struct SchedShared {
   float x[kFeatures], h1[32], h2[32], out[kVariants];
   double sums[3];
   float mf, mu;
-  int32_t v;
+  int32_t v, stop;
 };
 
 // Level k's variant, from level k-1's counters, computed by a whole
@@ -769,6 +779,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       mf += (double)__hip_atomic_load(&c[q * kCountFields + 4], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
     }
+    sh.stop = (k > 1 && nf == 0.0) ? 1 : 0;  // the previous level found nothing
     if (k > 1) {
       sh.sums[0] += nf;
       sh.sums[1] += mf;
@@ -791,6 +802,10 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     sh.mu = (float)mu0;
   }
   __syncthreads();
+  if (sh.stop) {
+    if (writer && t == 0) s.variant[k % kRing] = kStop;
+    return kStop;
+  }
   const bool use_model = (s.mode == 1) && s.model;
   if (use_model) {
     const float* W1 = s.model;
@@ -863,31 +878,35 @@ __device__ __forceinline__ void sched_clear_level(const SchedArgs& s, int32_t k)
   }
 }
 
-__global__ void schedule_kernel(SchedArgs s) {
+// One scheduled level k: every workgroup computes the level's variant from
+// level k-1's counters (same inputs and arithmetic everywhere, so all agree)
+// and runs the pull variant or the push scatter; workgroup 0 reports level
+// k-1 to the host, records the decision and the running totals, and clears
+// what level k+1 accumulates into.  The running totals are double-buffered
+// by level parity: level k reads buffer (k-1)&1 and writes buffer k&1.
+template <class S, int U, bool STAGED>
+__global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
+  extern __shared__ uint8_t lds_stage[];
   __shared__ SchedShared sh;
-  __shared__ int stop;
-  const int t = threadIdx.x;
-  const int k = s.level;
-  if (t == 0) {
-    stop = 0;
+  const int32_t k = a.level;
+  const bool writer = blockIdx.x == 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 3; ++i) sh.sums[i] = s.sums[4 * ((k - 1) & 1) + i];
+  const int32_t v = schedule_pick(s, k, sh, writer);
+  if (writer && threadIdx.x == 0) {
     if (k > 1) {
-      const uint64_t want = level_tag(s.run_id, k - 1);
-      const bool found = (s.any[(k - 1) % kRing] == want);
-      __hip_atomic_store(&s.report[(k - 1) % kRing], (want << 1) | (found ? 1u : 0u),
+      const uint64_t tag = level_tag(s.run_id, k - 1);
+      __hip_atomic_store(&s.report[(k - 1) % kRing], (tag << 1) | (v != kStop ? 1u : 0u),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      if (!found) {
-        s.variant[k % kRing] = kStop;
-        stop = 1;
-      }
     }
-    for (int i = 0; i < 3; ++i) sh.sums[i] = s.sums[i];
+    for (int i = 0; i < 3; ++i) s.sums[4 * (k & 1) + i] = sh.sums[i];
   }
-  __syncthreads();
-  if (stop) return;
-  sched_clear_level(s, k);
-  schedule_pick(s, k, sh, true);
-  if (t == 0)
-    for (int i = 0; i < 3; ++i) s.sums[i] = sh.sums[i];
+  if (v == kStop) return;
+  if (writer) sched_clear_level(s, k + 1);
+  if (v < kPullVariants)
+    level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], lds_stage);
+  else
+    push_scatter_body<S>(a, grid_wave(), grid_waves());
 }
 
 // Level-0 state of a scheduled run: the root is the frontier queue, and the
@@ -943,6 +962,10 @@ __global__ void persistent_sched_kernel(LevelArgs a, SchedArgs s, void* buf_a, v
     a.seg_n = s.seg_n + (k & 1);
     a.count_stats = count_stats && (k <= status[2]);
     const int32_t v = schedule_pick(s, k, sh, writer);
+    if (v == kStop) {  // level k-1 found nothing (every workgroup sees the same counters)
+      if (writer && threadIdx.x == 0) status[0] = k - 1;
+      return;
+    }
     if (writer && k < cap) sched_clear_level(s, k + 1);
     if (v < kPullVariants) {
       level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], lds_stage);
@@ -1111,7 +1134,9 @@ template <class S, bool STAGED>
 static void launch_level_u(int waves, int unroll, unsigned grid, const LevelArgs& a,
                            hipStream_t st) {
   const size_t lds = STAGED ? a.lds_bytes : 0;
-  if (unroll == 4)
+  if (a.val)  // the Sell-C-sigma comparator is built for one unroll depth
+    level_kernel<S, 8, STAGED, true><<<grid, waves * kC, lds, st>>>(a);
+  else if (unroll == 4)
     level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a);
   else if (unroll == 16)
     level_kernel<S, 16, STAGED><<<grid, waves * kC, lds, st>>>(a);
@@ -1151,7 +1176,6 @@ int launch_push(int semiring, const LevelArgs& a, void* stream) {
   constexpr unsigned kGroups = 2048, kThreads = 256;
   switch (semiring) {
 #define SS_PUSH(S)                                                  \
-  push_scatter_kernel<S><<<kGroups, kThreads, 0, st>>>(a);           \
   push_segments_kernel<S><<<kGroups, kThreads, 0, st>>>(a);          \
   push_post_kernel<S><<<kGroups / 2, kThreads, 0, st>>>(a);          \
   break;
@@ -1186,9 +1210,41 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   return s;
 }
 
-int launch_schedule(const SchedLaunch& p, int32_t level, uint32_t run_id, void* stream) {
-  schedule_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(sched_args(p, level, run_id));
-  return check_launch("schedule_kernel");
+template <class S, bool STAGED>
+static void launch_sched_level_u(int waves, int unroll, unsigned grid, const LevelArgs& a,
+                                 const SchedArgs& sa, hipStream_t st) {
+  const size_t lds = STAGED ? a.lds_bytes : 0;
+  if (unroll == 4)
+    sched_level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
+  else if (unroll == 16)
+    sched_level_kernel<S, 16, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
+  else
+    sched_level_kernel<S, 8, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
+}
+
+int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
+                       const LevelArgs& a, const SchedLaunch& p, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t groups = (a.n_units + waves - 1) / waves;
+  if (groups < 1) groups = 1;
+  if (max_groups > 0 && groups > max_groups) groups = max_groups;
+  const unsigned grid = (unsigned)groups;
+  const SchedArgs sa = sched_args(p, a.level, a.run_id);
+#define SS_SL(S)                                                      \
+  if (a.lds_bytes)                                                    \
+    launch_sched_level_u<S, true>(waves, unroll, grid, a, sa, st);    \
+  else                                                                \
+    launch_sched_level_u<S, false>(waves, unroll, grid, a, sa, st);   \
+  break;
+  switch (semiring) {
+    case SS_TROPICAL: SS_SL(Tropical)
+    case SS_REAL: SS_SL(Real)
+    case SS_BOOLEAN: SS_SL(Boolean)
+    case SS_SELMAX: SS_SL(SelMax)
+#undef SS_SL
+    default: return set_error(SS_EINVAL, "a scheduled run needs a single-root semiring");
+  }
+  return check_launch("sched_level_kernel");
 }
 
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream) {
@@ -1314,6 +1370,25 @@ int launch_batch_finalise(const Graph& g, const BatchWorkspace& b, int32_t rpg, 
   batch_finalise_kernel<<<blocks_for(g.n, 256), 256, 0, st>>>(
       g.n, g.num_graphs, g.d_voff, g.d_perm, b.vis, b.lvl, rpg, dist);
   return check_launch("batch_finalise_kernel");
+}
+
+__global__ void sell_build_kernel(const int32_t* col, int64_t cells, int32_t* scol,
+                                  int32_t* sval) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = col[i];
+    scol[i] = c >= 0 ? c : 0;
+    sval[i] = c >= 0 ? 1 : 0;
+  }
+}
+
+int launch_sell_build(const int32_t* col, int64_t cells, int32_t* scol, int32_t* sval,
+                      void* stream) {
+  if (cells <= 0) return SS_OK;
+  unsigned blocks = blocks_for(cells, 256);
+  if (blocks > 8192) blocks = 8192;
+  sell_build_kernel<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(col, cells, scol, sval);
+  return check_launch("sell_build_kernel");
 }
 
 int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count,

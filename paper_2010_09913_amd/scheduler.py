@@ -77,7 +77,7 @@ def evaluate(G: Graph, roots, semiring: str = "selmax", modes=None):
         G.bfs([int(roots[0])], semiring, schedule=mode)  # warm
         total = 0.0
         for root in roots:
-            res = G.bfs([int(root)], semiring, schedule=mode, timing=True)
+            res = G.bfs([int(root)], semiring, schedule=mode, timing="bfs")
             total += float(res.runs["bfs_ms"][0])
         torch.cuda.synchronize()
         out[mode] = total

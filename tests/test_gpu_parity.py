@@ -210,8 +210,10 @@ def test_edge_cases(ss):
         with pytest.raises(ss.SlimSellError) as ei:
             G.bfs(kw.pop("roots"), "tropical", **kw)
         assert ei.value.code == code
-    with pytest.raises(ss.SlimSellError):
-        G.bfs([0], "tropical", parent=torch.empty((1, 3), dtype=torch.int32, device="cuda"))
+    # parents with a non-sel-max semiring come from the DP transformation
+    par = torch.full((1, 3), -7, dtype=torch.int32, device="cuda")
+    G.bfs([0], "tropical", parent=par)
+    assert par.cpu().tolist() == [[0, 0, 1]]
     with pytest.raises(ss.SlimSellError):
         G.bfs([0], "boolean", real_val=torch.empty((1, 3), dtype=torch.float32, device="cuda"))
     # the level cap is reported, not hung on

@@ -152,6 +152,11 @@ def test_model_that_prefers_one_variant_and_nan_fallback(ss):
     ss.sched_clear()
     res = _run(G, root, "selmax", "learned")   # no model: heuristic
     np.testing.assert_array_equal(res.levels["variant"][0], heur.levels["variant"][0])
+    # whole-BFS timing only: no per-level events
+    for pers in (False, True):
+        rt = G.bfs([root], "selmax", schedule="heuristic", timing="bfs", persistent=pers)
+        _check(rt, ex, "selmax")
+        assert rt.runs["bfs_ms"][0] > 0 and rt.runs["kernel_ms"][0] == 0
     with pytest.raises(ss.SlimSellError):
         G.bfs([root], "selmax", schedule="heuristic", slimwork=1)
     with pytest.raises(ss.SlimSellError):

@@ -160,3 +160,20 @@ def test_build_without_device_reports_unsupported_or_builds():
     with pytest.raises(ss.SlimSellError) as ei:
         ss.Graph([0, 1], [1, 2], 3)
     assert ei.value.code in (_native.SS_EUNSUP, _native.SS_EHIP)
+
+
+def test_storage_against_table_sizes():
+    """Table "sizes": SlimSell needs about half of Sell-C-sigma (which stores val
+    as well as col) and less than CSR, and it is smaller than AL exactly when
+    the padding stays below n(1 - 2/C) (the inequality of Section III-B)."""
+    import paper_2010_09913_amd as ss
+    for e in (graphgen.rmat(14, 16, seed=1), graphgen.er(1 << 14, 40 << 14, seed=2)):
+        for sigma in (0, 1024, 1):
+            L = ss.layout_build(e.src, e.dst, e.n, sigma=sigma, arrays=False)
+            E, P, nc = L.entries, L.cells - L.entries, L.n_chunks
+            assert nc * 64 == e.n
+            slim, sell, csr, al = E + P + 2 * nc, 2 * (E + P) + 2 * nc, 2 * E + e.n, E + e.n
+            assert 0.5 < slim / sell < 0.51
+            if sigma == 0:
+                assert slim < csr
+            assert (slim < al) == (P < e.n * (1 - 2 / 64))
