@@ -372,17 +372,28 @@ int slimsell_dp_parents(ss_graph* g, const int32_t* dist, int32_t num_roots, int
  * log-time of each variant; the smallest wins.  Parameter layout (1412
  * floats): W1[32][6], b1[32], W2[32][32], b2[32], W3[4][32], b3[4].
  * Features, in order: log2(1+n_f)/log2 n; log2(1+m_f)/log2(1+2m);
- * log2(1+m_u)/log2(1+2m); n_u/n; clamp(log2((1+n_f)/(1+n_f,prev))/8, +-1);
- * clamp(log2((1+m_f)/(1+m_u))/16, +-1) -- n_f, m_f: vertices and edges of
- * the frontier; n_u, m_u: vertices and edges not yet discovered; m:
- * undirected edges.  All are ratios, so they carry across graph sizes.
+ * log2(1+m_u)/log2(1+2m); clamp(log2((1+m_f)/(1+n_f))/16, 0, 1);
+ * clamp(log2((1+m_u)/n)/8, +-1); clamp(log2((1+m_f)/(1+m_u))/16, +-1) --
+ * n_f, m_f: vertices and edge ends of the frontier; m_u: edge ends of the
+ * vertices not yet discovered; n vertices, m undirected edges.  They measure
+ * the push work (m_f) and the pull work (m_u) on log scales relative to the
+ * graph, so they carry across graph sizes.
+ *
+ * A model may also carry its training domain: count = 1412 + 2 + 6K floats,
+ * the parameters, then tau > 0, K (1..1024, as a float) and K feature
+ * vectors.  A level whose features lie farther than tau (Euclidean) from all
+ * K vectors is decided by the fixed heuristic, as are levels with non-finite
+ * scores.
  */
 #define SS_SCHED_PARAMS 1412
 #define SS_SCHED_FEATURES 6
 #define SS_SCHED_VARIANTS 4
 
-/* Install the process-wide model (host float[1412]); non-finite values are
- * accepted, and the fixed heuristic then takes over at run time. */
+/* Install the process-wide model: host float[count], count = 1412 (the
+ * parameters) or 1412 + 2 + 6K (parameters and training domain, see above);
+ * copied.  Non-finite parameters are accepted, and the fixed heuristic then
+ * takes over at run time.  Errors: SS_EINVAL for any other count, tau <= 0,
+ * K outside 1..1024 or non-finite anchors. */
 int slimsell_sched_load(const float* weights, int64_t count);
 /* Remove the model (learned scheduling then uses the fixed heuristic). */
 int slimsell_sched_clear(void);

@@ -70,8 +70,11 @@ def loss_only(w, x, y):
 
 def features(dist, degree, n: int, entries: int):
     """Features of levels 1..D+1 of one BFS: row k-1 describes level k.
-    n_f, m_f: vertices and degree sum at distance k-1; n_u, m_u: vertices and
-    degree sum at distance >= k or unreachable; prev: vertices at k-2."""
+    n_f, m_f: vertices and degree sum at distance k-1; m_u: degree sum at
+    distance >= k or unreachable.  The frontier's size (vertices, edges) and
+    the unvisited edges relative to the graph, the frontier's mean degree, the
+    unvisited edges per vertex of the graph, and the frontier/unvisited edge
+    ratio, all on log scales."""
     dist = np.asarray(dist)
     deg = np.asarray(degree, np.float64)
     iters = int(dist.max()) + 1
@@ -83,13 +86,12 @@ def features(dist, degree, n: int, entries: int):
         before = (dist >= 0) & (dist < k)
         nf = float(at.sum())
         mf = float(deg[at].sum())
-        nu = float(n - before.sum())
-        mu = float(entries - deg[before].sum())
-        prev = float((dist == k - 2).sum()) if k >= 2 else 0.0
-        growth = np.clip(np.log2((1.0 + nf) / (1.0 + prev)) / 8.0, -1.0, 1.0)
-        ratio = np.clip(np.log2((1.0 + mf) / (1.0 + max(mu, 0.0))) / 16.0, -1.0, 1.0)
-        rows.append([np.log2(1.0 + nf) / l2n, np.log2(1.0 + mf) / l2m,
-                     np.log2(1.0 + max(mu, 0.0)) / l2m, max(nu, 0.0) / n, growth, ratio])
+        mu = max(float(entries - deg[before].sum()), 0.0)
+        fdeg = np.clip(np.log2((1.0 + mf) / (1.0 + nf)) / 16.0, 0.0, 1.0)
+        udeg = np.clip(np.log2((1.0 + mu) / n) / 8.0, -1.0, 1.0)
+        ratio = np.clip(np.log2((1.0 + mf) / (1.0 + mu)) / 16.0, -1.0, 1.0)
+        rows.append([np.log2(1.0 + nf) / l2n, np.log2(1.0 + mf) / l2m, np.log2(1.0 + mu) / l2m,
+                     fdeg, udeg, ratio])
     return np.array(rows)
 
 
@@ -107,3 +109,37 @@ def heuristic(dist, degree, n: int, entries: int, pull_variant: int):
         pull = mf * 14.0 > mu
         out.append(pull_variant if pull else 3)
     return np.array(out)
+
+
+def split_domain(model):
+    """A model is the 1412 MLP parameters, optionally followed by its training
+    domain: tau, K and K feature vectors.  Returns (params, tau, anchors)."""
+    model = np.asarray(model, np.float64)
+    w = model[:PARAMS]
+    if model.size == PARAMS:
+        return w, None, None
+    tau, k = float(model[PARAMS]), int(model[PARAMS + 1])
+    return w, tau, model[PARAMS + 2: PARAMS + 2 + 6 * k].reshape(k, 6)
+
+
+def nearest_anchor_sq(x, anchors):
+    """Squared distance from each feature row to its nearest anchor, in float32
+    (the precision the schedule decides in)."""
+    x = np.asarray(x, np.float32)
+    a = np.asarray(anchors, np.float32)
+    d = x[:, None, :] - a[None, :, :]
+    return (d * d).sum(-1, dtype=np.float32).min(1)
+
+
+def choose(model, x, heuristic_variants):
+    """The learned schedule's decision per level: the variant of smallest
+    predicted log-time when the level lies within tau of a training anchor
+    (or the model carries no domain) and the scores are finite, otherwise
+    the heuristic's variant."""
+    w, tau, anchors = split_domain(model)
+    scores = forward(w, x)
+    pick = np.argmin(scores, axis=1)
+    ok = np.all(np.isfinite(scores), axis=1)
+    if anchors is not None:
+        ok &= nearest_anchor_sq(x, anchors) <= np.float32(tau) * np.float32(tau)
+    return np.where(ok, pick, np.asarray(heuristic_variants)), scores

@@ -400,7 +400,8 @@ def _fp(a):
 
 
 def sched_load(weights) -> None:
-    """Install the process-wide scheduler model (1412 float32 parameters)."""
+    """Install the process-wide scheduler model: 1412 float32 parameters,
+    optionally followed by its training domain (tau, K, K x 6 features)."""
     w = _f32(weights).reshape(-1)
     check(_native.load().slimsell_sched_load(_fp(w), w.shape[0]))
 

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <immintrin.h>
 #include <new>
@@ -202,7 +203,7 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.variant, kRing))) return rc;
   if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kCountSlots * kCountFields))) return rc;
   if ((rc = dalloc(&ws.sched_sums, 8))) return rc;
-  if ((rc = dalloc(&ws.model, kModelSize))) return rc;
+  if ((rc = dalloc(&ws.model, kModelCap))) return rc;
   ws.sched_log_cap = std::min<int64_t>((int64_t)g.n + 2, 65536);
   if ((rc = dalloc(&ws.sched_log, ws.sched_log_cap * 12))) return rc;
   // segments of long frontier rows: at most one per frontier row plus one per
@@ -281,6 +282,8 @@ struct RunPlan {
   UnitList* ul = nullptr;
   UnitList* vul[kPullVariants] = {nullptr, nullptr, nullptr};  // pull variants
   bool has_model = false;
+  int32_t n_anchors = 0;  // training-domain anchors carried by the model
+  float tau = 0.f;
 };
 
 // Per-call record of what was launched, for the statistics epilogue.
@@ -345,9 +348,13 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
     uint64_t version = 0;
     p->has_model = (p->schedule == 1) && sched_model(&host, &version);
     if (p->has_model && g.ws.model_version != version) {
-      SS_HIP(hipMemcpy(g.ws.model, host.data(), sizeof(float) * kModelSize, hipMemcpyHostToDevice));
+      SS_HIP(hipMemcpy(g.ws.model, host.data(), sizeof(float) * host.size(),
+                       hipMemcpyHostToDevice));
       g.ws.model_version = version;
     }
+    p->n_anchors = p->has_model && (int64_t)host.size() > kModelSize
+                       ? (int32_t)host[kModelSize + 1] : 0;
+    p->tau = p->n_anchors ? host[kModelSize] : 0.f;
   }
   p->timing = (o->flags & (SS_STATS_TIME | SS_STATS_TIME_BFS)) != 0;
   p->level_events = (o->flags & SS_STATS_TIME) && !(o->flags & SS_STATS_TIME_BFS);
@@ -442,6 +449,9 @@ static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
   sl.ring_ctr = g.ws.ring_ctr;
   sl.sums = g.ws.sched_sums;
   sl.model = p.has_model ? g.ws.model : nullptr;
+  sl.anchors = p.n_anchors ? g.ws.model + kModelSize + 2 : nullptr;
+  sl.n_anchors = p.n_anchors;
+  sl.tau2 = p.tau * p.tau;
   sl.log = g.ws.sched_log;
   sl.log_cap = (int32_t)g.ws.sched_log_cap;
   sl.mode = p.schedule;
@@ -673,10 +683,21 @@ const char* slimsell_last_error(void) { return g_last_error.c_str(); }
 const char* slimsell_version(void) { return "slimsell-mi355x 0.1 (gfx950)"; }
 
 int slimsell_sched_load(const float* w, int64_t count) {
-  if (!w || count != kModelSize)
-    return set_error(SS_EINVAL, "the scheduler model has exactly 1412 parameters");
+  if (!w || count < kModelSize)
+    return set_error(SS_EINVAL, "the scheduler model has 1412 parameters");
+  if (count > kModelSize) {
+    // training domain: tau, K, K anchors of 6 features
+    const float tau = count >= kModelSize + 2 ? w[kModelSize] : -1.f;
+    const float kf = count >= kModelSize + 2 ? w[kModelSize + 1] : -1.f;
+    if (!(tau > 0.f) || !std::isfinite(tau) || !(kf >= 1.f) || kf > (float)kMaxAnchors ||
+        kf != std::floor(kf) || count != kModelSize + 2 + (int64_t)kf * kFeatures)
+      return set_error(SS_EINVAL,
+                       "model domain must be tau > 0, K in 1..1024, then K x 6 features");
+    for (int64_t i = kModelSize + 2; i < count; ++i)
+      if (!std::isfinite(w[i])) return set_error(SS_EINVAL, "model anchors must be finite");
+  }
   std::lock_guard<std::mutex> lk(g_model_mu);
-  g_model.assign(w, w + kModelSize);
+  g_model.assign(w, w + count);
   g_model_version = ++g_model_counter;
   return SS_OK;
 }
@@ -738,6 +759,15 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
   ss_graph* g = new (std::nothrow) ss_graph();
   if (!g) return set_error(SS_ENOMEM, "host allocation failed");
   (void)hipGetDevice(&g->device);
+  {
+    // dynamic LDS a kernel may ask for: the device's limit, at most 64 KiB
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) !=
+            hipSuccess ||
+        lds < 0)
+      lds = 0;
+    g->lds_cap = std::min(lds, 64 * 1024);
+  }
   g->n = L->n;
   g->n_pad = L->n_pad;
   g->sigma = L->sigma;

@@ -27,6 +27,47 @@ __device__ __forceinline__ uint32_t off_of(int32_t c, int shift) {
 __device__ __forceinline__ void keep(int32_t v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// LDS-staged prefix of the gathered vector.  With a full sort the rows of
+// highest degree (the most gathered) come first, so each workgroup copies the
+// first `bytes` of the vector into LDS once per level; a gather whose byte
+// offset falls inside reads LDS, any other reads global memory.  The two
+// loads are issued branch-free: the LDS read uses a clamped address and is
+// masked, the buffer load gets an out-of-range offset when LDS serves it.
+struct Stage {
+  const uint8_t* lds;
+  uint32_t bytes;  // 0 = nothing staged
+};
+
+template <bool STAGED>
+__device__ __forceinline__ uint32_t gather_b32(Rsrc r, Stage st, uint32_t off) {
+  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  const bool in = off < st.bytes;
+  uint32_t l = *reinterpret_cast<const uint32_t*>(st.lds + (in ? off : 0u));
+  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b32(r, in ? kOob : off, 0, 0);
+  return (in ? l : 0u) | g;
+}
+template <bool STAGED>
+__device__ __forceinline__ uint32_t gather_b8(Rsrc r, Stage st, uint32_t off) {
+  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+  const bool in = off < st.bytes;
+  const uint32_t l = st.lds[in ? off : 0u];
+  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b8(r, in ? kOob : off, 0, 0);
+  return (in ? l : 0u) | g;
+}
+template <bool STAGED>
+__device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint32_t off) {
+  unsigned long long l = 0ull;
+  bool in = false;
+  if (STAGED) {
+    in = off < st.bytes;
+    l = *reinterpret_cast<const unsigned long long*>(st.lds + (in ? off : 0u));
+  }
+  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, in ? kOob : off, 0, 0);
+  const unsigned long long g = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
+  return (in ? l : 0ull) | g;
+}
+
+
 __device__ __forceinline__ int32_t wave_max(int32_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {

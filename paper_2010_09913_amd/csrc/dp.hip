@@ -16,10 +16,15 @@
 // combine with atomicMax, which is order-independent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "internal.h"
 
 namespace ss {
+
+constexpr int64_t kDpCodeLds = 48 * 1024;  // codes of the first 192K rows
+constexpr int64_t kDpVLds = 16 * 1024;     // v of the first 4K rows
 
 struct DpArgs {
   const int32_t* col;
@@ -34,6 +39,7 @@ struct DpArgs {
   const uint8_t* code;  // 2-bit distance mod 3 per row, 4 rows per byte
   int32_t* acc;         // largest v of a qualifying neighbour, per row
   uint32_t n_pad;
+  uint32_t code_lds, v_lds;  // bytes of codes and of v staged in LDS (multiples of 16)
 };
 
 // Row-order distances and their codes, one thread per row.  n_pad is a
@@ -51,13 +57,29 @@ __global__ void dp_prep_kernel(int32_t n_pad, const int32_t* v, const int32_t* d
   if ((threadIdx.x & 3) == 0) code[r >> 2] = (uint8_t)(c | (c1 << 2) | (c2 << 4) | (c3 << 6));
 }
 
-template <int U>
+// With STAGED, each workgroup first copies the first code_lds bytes of the
+// codes and the first v_lds bytes of v into LDS: with a full sort the rows of
+// highest degree, the most gathered, come first.
+template <int U, bool STAGED>
 __global__ void dp_sweep_kernel(DpArgs a) {
+  extern __shared__ uint8_t lds[];
   const int lane = threadIdx.x & (kC - 1);
   const int wave = threadIdx.x / kC;
   const int waves = blockDim.x / kC;
   const Rsrc rc = make_rsrc(a.code, a.n_pad / 4u);
   const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
+  Stage sc{lds, 0u}, sv{lds + a.code_lds, 0u};
+  if (STAGED) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(a.code);
+    const uint4* v4 = reinterpret_cast<const uint4*>(a.v);
+    uint4* d4 = reinterpret_cast<uint4*>(lds);
+    const uint32_t nc = a.code_lds / 16u, nv = a.v_lds / 16u;
+    for (uint32_t i = threadIdx.x; i < nc + nv; i += blockDim.x)
+      d4[i] = i < nc ? c4[i] : v4[i - nc];
+    __syncthreads();
+    sc.bytes = a.code_lds;
+    sv.bytes = a.v_lds;
+  }
   for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < a.n_units;
        u += (int64_t)gridDim.x * waves) {
     const Unit w = a.units[u];
@@ -85,13 +107,12 @@ __global__ void dp_sweep_kernel(DpArgs a) {
         uint32_t b[U];
 #pragma unroll
         for (int t = 0; t < U; ++t)
-          b[t] = __builtin_amdgcn_raw_buffer_load_b8(rc, cc[t] >= 0 ? (uint32_t)cc[t] >> 2 : kOob,
-                                                     0, 0);
+          b[t] = gather_b8<STAGED>(rc, sc, cc[t] >= 0 ? (uint32_t)cc[t] >> 2 : kOob);
         int32_t x[U];
 #pragma unroll
         for (int t = 0; t < U; ++t) {
           const bool hit = cc[t] >= 0 && ((b[t] >> ((cc[t] & 3) * 2)) & 3u) == want;
-          x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit ? (uint32_t)cc[t] << 2 : kOob, 0, 0);
+          x[t] = (int32_t)gather_b32<STAGED>(rv, sv, hit ? (uint32_t)cc[t] << 2 : kOob);
         }
 #pragma unroll
         for (int t = 0; t < U; ++t) best = x[t] > best ? x[t] : best;
@@ -99,11 +120,9 @@ __global__ void dp_sweep_kernel(DpArgs a) {
       }
       for (; j < hi; ++j) {
         const int32_t c1 = on ? __builtin_nontemporal_load(p) : -1;
-        const uint32_t b1 =
-            __builtin_amdgcn_raw_buffer_load_b8(rc, c1 >= 0 ? (uint32_t)c1 >> 2 : kOob, 0, 0);
+        const uint32_t b1 = gather_b8<STAGED>(rc, sc, c1 >= 0 ? (uint32_t)c1 >> 2 : kOob);
         const bool hit = c1 >= 0 && ((b1 >> ((c1 & 3) * 2)) & 3u) == want;
-        const int32_t x1 =
-            __builtin_amdgcn_raw_buffer_load_b32(rv, hit ? (uint32_t)c1 << 2 : kOob, 0, 0);
+        const int32_t x1 = (int32_t)gather_b32<STAGED>(rv, sv, hit ? (uint32_t)c1 << 2 : kOob);
         best = x1 > best ? x1 : best;
         p += kC;
       }
@@ -151,16 +170,37 @@ int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t
   a.code = ws.g;
   a.acc = ws.acc;
   a.n_pad = (uint32_t)g.n_pad;
+  // LDS prefixes: up to 48 KiB of codes and 16 KiB of v, within what the
+  // device gives a workgroup
+  const int64_t cap = g.lds_cap > 0 ? g.lds_cap : 0;
+  int64_t cb = std::min<int64_t>(g.n_pad / 4, kDpCodeLds) / 16 * 16;
+  int64_t vb = std::min<int64_t>(g.n_pad * 4, kDpVLds) / 16 * 16;
+  if (cb + vb > cap) {
+    cb = std::min<int64_t>(cb, cap) / 16 * 16;
+    vb = std::max<int64_t>(0, cap - cb) / 16 * 16;
+  }
+  a.code_lds = (uint32_t)cb;
+  a.v_lds = (uint32_t)vb;
   if (ul.count > 0) {
     int64_t blocks = (ul.count + waves - 1) / waves;
     if (max_groups > 0 && blocks > max_groups) blocks = max_groups;
     const dim3 grid((unsigned)blocks), block((unsigned)(waves * kC));
-    if (unroll == 4)
-      dp_sweep_kernel<4><<<grid, block, 0, st>>>(a);
-    else if (unroll == 16)
-      dp_sweep_kernel<16><<<grid, block, 0, st>>>(a);
-    else
-      dp_sweep_kernel<8><<<grid, block, 0, st>>>(a);
+    const size_t lds = (size_t)(cb + vb);
+    if (lds == 0) {
+      if (unroll == 4)
+        dp_sweep_kernel<4, false><<<grid, block, 0, st>>>(a);
+      else if (unroll == 16)
+        dp_sweep_kernel<16, false><<<grid, block, 0, st>>>(a);
+      else
+        dp_sweep_kernel<8, false><<<grid, block, 0, st>>>(a);
+    } else {
+      if (unroll == 4)
+        dp_sweep_kernel<4, true><<<grid, block, lds, st>>>(a);
+      else if (unroll == 16)
+        dp_sweep_kernel<16, true><<<grid, block, lds, st>>>(a);
+      else
+        dp_sweep_kernel<8, true><<<grid, block, lds, st>>>(a);
+    }
     if ((rc = check_launch("dp_sweep_kernel"))) return rc;
   }
   dp_finalise_kernel<<<rows_blocks, 256, 0, st>>>((int32_t)g.n_pad, g.d_v, ws.d, ws.acc, parent);

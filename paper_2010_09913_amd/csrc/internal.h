@@ -84,7 +84,7 @@ struct Workspace {
   double* sched_sums = nullptr;        // [8] running totals for the features, 2 buffers
   float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
   int64_t sched_log_cap = 0;
-  float* model = nullptr;              // [kModelSize] device copy of the scheduler model
+  float* model = nullptr;              // [kModelCap] device copy of the scheduler model
   uint64_t model_version = 0;          // version of the process model copied there
   int2* segs = nullptr;                 // push segments: capacity seg_cap
   int64_t seg_cap = 0;
@@ -122,6 +122,11 @@ constexpr int kPush = 3;
 constexpr int kStop = -2;        // variant tag of a level past the end of the BFS
 constexpr int kModelSize = 6 * 32 + 32 + 32 * 32 + 32 + 32 * 4 + 4;  // 1412 parameters
 constexpr int kFeatures = 6;
+// A model may carry its training domain after the parameters: tau, K, then K
+// feature vectors (anchors); a level farther than tau from every anchor falls
+// back to the fixed heuristic.
+constexpr int kMaxAnchors = 1024;
+constexpr int kModelCap = kModelSize + 2 + kMaxAnchors * kFeatures;
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
 
 struct Graph {
@@ -214,6 +219,9 @@ struct SchedLaunch {
   unsigned long long* ring_ctr;
   double* sums;
   const float* model;
+  const float* anchors;   // training-domain anchors [n_anchors][6] or nullptr
+  int32_t n_anchors;
+  float tau2;             // squared distance beyond which the heuristic decides
   float* log;
   int32_t log_cap;
   int32_t mode;

@@ -44,47 +44,6 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // post-processing of the listing in Section III-A; and publish(chunk, mask),
 // which stores the chunk's new frontier word where the frontier is a bitmap.
 
-// LDS-staged prefix of the gathered vector.  With a full sort the rows of
-// highest degree (the most gathered) come first, so each workgroup copies the
-// first `bytes` of the vector into LDS once per level; a gather whose byte
-// offset falls inside reads LDS, any other reads global memory.  The two
-// loads are issued branch-free: the LDS read uses a clamped address and is
-// masked, the buffer load gets an out-of-range offset when LDS serves it.
-struct Stage {
-  const uint8_t* lds;
-  uint32_t bytes;  // 0 = nothing staged
-};
-
-template <bool STAGED>
-__device__ __forceinline__ uint32_t gather_b32(Rsrc r, Stage st, uint32_t off) {
-  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-  const bool in = off < st.bytes;
-  uint32_t l = *reinterpret_cast<const uint32_t*>(st.lds + (in ? off : 0u));
-  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b32(r, in ? kOob : off, 0, 0);
-  return (in ? l : 0u) | g;
-}
-template <bool STAGED>
-__device__ __forceinline__ uint32_t gather_b8(Rsrc r, Stage st, uint32_t off) {
-  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
-  const bool in = off < st.bytes;
-  const uint32_t l = st.lds[in ? off : 0u];
-  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b8(r, in ? kOob : off, 0, 0);
-  return (in ? l : 0u) | g;
-}
-template <bool STAGED>
-__device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint32_t off) {
-  unsigned long long l = 0ull;
-  bool in = false;
-  if (STAGED) {
-    in = off < st.bytes;
-    l = *reinterpret_cast<const unsigned long long*>(st.lds + (in ? off : 0u));
-  }
-  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, in ? kOob : off, 0, 0);
-  const unsigned long long g = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
-  return (in ? l : 0ull) | g;
-}
-
-
 // Tropical (min, +): x_k = f_k = A' (x) f_{k-1}, A' has 1 on edges, 0 on the
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
@@ -350,6 +309,44 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
   if (!on) return acc;
   const int32_t* __restrict__ pv = VAL ? a.val + (p - a.col) : nullptr;
   int32_t j = 0;
+  if (ncols >= 2 * U) {
+    // Software pipeline: the next block's col (and val) loads are in flight
+    // while this block's gathers (which depend on its col values) are
+    // served, so a block costs one memory latency instead of two.  (A second
+    // block of depth measured no faster and costs U more registers.)
+    int32_t c[U], w[U], nc[U], nw[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+      if (VAL) w[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+    }
+    p += (int64_t)U * kC;
+    if (VAL) pv += (int64_t)U * kC;
+    for (j = U; j + U <= ncols; j += U) {
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        nc[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+        if (VAL) nw[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+      }
+      if (VAL) {
+#pragma unroll
+        for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+      }
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        c[t] = nc[t];
+        if (VAL) w[t] = nw[t];
+      }
+      p += (int64_t)U * kC;
+      if (VAL) pv += (int64_t)U * kC;
+    }
+    if (VAL) {
+#pragma unroll
+      for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+    }
+    acc = S::template block<U, STAGED>(a, r, st, c, acc);
+  }
   for (; j + U <= ncols; j += U) {
     int32_t c[U];
 #pragma unroll
@@ -745,6 +742,9 @@ struct SchedArgs {
   unsigned long long* ring_ctr;
   double* sums;           // [0] discovered so far, [1] their degrees, [2] previous frontier size
   const float* model;     // nullptr = no model
+  const float* anchors;   // the model's training domain [n_anchors][6], or nullptr
+  int32_t n_anchors;
+  float tau2;             // squared distance to the nearest anchor the model may answer at
   float* log;             // [log_cap * 12]
   int32_t log_cap;
   int32_t mode;           // 1 learned, 2 heuristic, 3.. forced variant (mode - 3)
@@ -757,6 +757,7 @@ struct SchedArgs {
 // size.
 struct SchedShared {
   float x[kFeatures], h1[32], h2[32], out[kVariants];
+  float near[64];  // per-thread nearest squared anchor distance (first 64 threads)
   double sums[3];
   float mf, mu;
   int32_t v, stop;
@@ -784,18 +785,18 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       sh.sums[0] += nf;
       sh.sums[1] += mf;
     }
-    const double nu = s.n - sh.sums[0], mu = s.two_m - sh.sums[1];
+    const double mu = s.two_m - sh.sums[1];
     const double l2n = log2(s.n > 2.0 ? s.n : 2.0), l2m = log2(1.0 + (s.two_m > 1.0 ? s.two_m : 1.0));
-    double growth = log2((1.0 + nf) / (1.0 + sh.sums[2])) / 8.0;
-    growth = growth > 1.0 ? 1.0 : (growth < -1.0 ? -1.0 : growth);
     const double mu0 = mu > 0.0 ? mu : 0.0;
-    double ratio = log2((1.0 + mf) / (1.0 + mu0)) / 16.0;
-    ratio = ratio > 1.0 ? 1.0 : (ratio < -1.0 ? -1.0 : ratio);
-    sh.x[0] = (float)(log2(1.0 + nf) / l2n);
-    sh.x[1] = (float)(log2(1.0 + mf) / l2m);
-    sh.x[2] = (float)(log2(1.0 + mu0) / l2m);
-    sh.x[3] = (float)((nu > 0.0 ? nu : 0.0) / s.n);
-    sh.x[4] = (float)growth;
+    const double lnf = log2(1.0 + nf), lmf = log2(1.0 + mf), lmu = log2(1.0 + mu0);
+    const double fdeg = fmin(fmax((lmf - lnf) / 16.0, 0.0), 1.0);
+    const double udeg = fmin(fmax(log2((1.0 + mu0) / s.n) / 8.0, -1.0), 1.0);
+    const double ratio = fmin(fmax((lmf - lmu) / 16.0, -1.0), 1.0);
+    sh.x[0] = (float)(lnf / l2n);
+    sh.x[1] = (float)(lmf / l2m);
+    sh.x[2] = (float)(lmu / l2m);
+    sh.x[3] = (float)fdeg;
+    sh.x[4] = (float)udeg;
     sh.x[5] = (float)ratio;
     sh.sums[2] = nf;
     sh.mf = (float)mf;
@@ -806,7 +807,29 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     if (writer && t == 0) s.variant[k % kRing] = kStop;
     return kStop;
   }
-  const bool use_model = (s.mode == 1) && s.model;
+  bool use_model = (s.mode == 1) && s.model;
+  if (use_model && s.anchors) {
+    // nearest anchor: threads 0..63 each scan a strided share, then a min
+    // tree (min is exact, so every workgroup gets the same value)
+    if (t < 64) {
+      float best = INFINITY;
+      for (int i = t; i < s.n_anchors; i += 64) {
+        float d2 = 0.f;
+        for (int f = 0; f < kFeatures; ++f) {
+          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
+          d2 = fmaf(df, df, d2);
+        }
+        best = d2 < best ? d2 : best;
+      }
+      sh.near[t] = best;
+    }
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (t < w) sh.near[t] = sh.near[t + w] < sh.near[t] ? sh.near[t + w] : sh.near[t];
+      __syncthreads();
+    }
+    use_model = sh.near[0] <= s.tau2;  // outside the training domain: the heuristic decides
+  }
   if (use_model) {
     const float* W1 = s.model;
     const float* b1 = W1 + 32 * kFeatures;
@@ -1201,6 +1224,9 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.ring_ctr = p.ring_ctr;
   s.sums = p.sums;
   s.model = p.model;
+  s.anchors = p.anchors;
+  s.n_anchors = p.n_anchors;
+  s.tau2 = p.tau2;
   s.log = p.log;
   s.log_cap = p.log_cap;
   s.mode = p.mode;

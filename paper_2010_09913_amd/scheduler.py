@@ -7,7 +7,9 @@ of that BFS, and four such runs give the full per-level timing table.  The
 features of a level are the same in all four runs.  Targets are the
 log-times of the four variants centred per level and scaled by one deviation
 (so the argmin is unchanged and only relative costs are learned); the MLP is
-trained on the GPU by the library's own kernels (slimsell_sched_train).
+trained on the GPU by the library's own kernels (slimsell_sched_train).  The
+saved model carries its training domain (the training features and a radius
+tau), outside which the fixed heuristic decides.
 
 Usage (writes the model next to this file):
   python -m paper_2010_09913_amd.scheduler --out paper_2010_09913_amd/models/sched_selmax.npy
@@ -66,6 +68,24 @@ def train(X, T, steps: int = 3000, lr: float = 3e-3, seed: int = 0):
     y, mu, sd = standardise(T)
     w, losses = sched_train(X.astype(np.float32), y, steps=steps, lr=lr, seed=seed)
     return w, losses, (mu, sd)
+
+
+def with_domain(w, X, quantile: float = 0.95, max_anchors: int = 1024):
+    """The model with its training domain appended: the training features as
+    anchors (an evenly spaced subset if there are more than max_anchors) and
+    tau = the given quantile of each sample's distance to its nearest other
+    sample, so a level the training data does not cover is left to the
+    heuristic."""
+    X = np.asarray(X, np.float64)
+    if len(X) > max_anchors:
+        X = X[np.linspace(0, len(X) - 1, max_anchors).astype(np.int64)]
+    d = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    tau = float(np.quantile(d.min(1), quantile)) if len(X) > 1 else 0.1
+    tau = max(tau, 1e-3)
+    return np.concatenate([np.asarray(w, np.float32).ravel(),
+                           np.array([tau, len(X)], np.float32),
+                           X.astype(np.float32).ravel()]), tau
 
 
 def evaluate(G: Graph, roots, semiring: str = "selmax", modes=None):
@@ -132,8 +152,10 @@ def main() -> int:
                       "best_possible_ms": float(best_possible),
                       "forced_ms": {v: float(T[:, i].sum()) for i, v in enumerate(VARIANTS)},
                       "graphs": meta}), flush=True)
+    model, tau = with_domain(w, X)
+    print(json.dumps({"domain_tau": tau, "anchors": int(min(len(X), 1024))}), flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    np.save(args.out, w.astype(np.float32))
+    np.save(args.out, model)
     np.save(os.path.splitext(args.out)[0] + "_data.npy",
             np.concatenate([X, T], axis=1).astype(np.float32))
     return 0

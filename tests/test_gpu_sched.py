@@ -162,3 +162,48 @@ def test_model_that_prefers_one_variant_and_nan_fallback(ss):
     with pytest.raises(ss.SlimSellError):
         ss.sched_load(np.zeros(10, np.float32))
     G.close()
+
+
+def test_training_domain_decides_between_model_and_heuristic(ss):
+    e = _graphs()["rmat"]
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e)
+    rng = np.random.default_rng(5)
+    w = rng.normal(0, 0.5, mlp.PARAMS).astype(np.float32)
+    for root in graphgen.pick_roots(e, 2, seed=46):
+        ex = oracle.expected(g, int(root))
+        it = ex.iterations
+        feats = mlp.features(ex.dist, g.degree, g.n, g.entries).astype(np.float32)
+        heur = mlp.heuristic(ex.dist, g.degree, g.n, g.entries, 1)
+        cases = {
+            # every level on an anchor: the model decides everywhere
+            "inside": (feats, 1e-3),
+            # anchors far from every level: the heuristic decides everywhere
+            "outside": (feats + 5.0, 0.5),
+            # every other level is an anchor, tau below the gaps: mixed
+            "mixed": (feats[::2], 1e-3),
+        }
+        for name, (anchors, tau) in cases.items():
+            note("domain", root, name)
+            model = np.concatenate([w, [tau, len(anchors)], anchors.ravel()]).astype(np.float32)
+            ss.sched_load(model)
+            res = _run(G, int(root), "selmax", "learned")
+            _check(res, ex, "selmax")
+            got = res.levels["variant"][0][:it]
+            want, scores = mlp.choose(model, feats, heur)
+            # compare away from ties of the scores and of the distance test
+            srt = np.sort(scores, axis=1)
+            d2 = mlp.nearest_anchor_sq(feats, anchors)
+            clear = ((srt[:, 1] - srt[:, 0]) > 1e-3) & (np.abs(d2 - np.float32(tau) ** 2) > 1e-6)
+            np.testing.assert_array_equal(got[clear], want[clear])
+            if name == "outside":
+                np.testing.assert_array_equal(got, heur)
+            # the persistent form decides the same
+            resp = _run(G, int(root), "selmax", "learned", persistent=True)
+            _check(resp, ex, "selmax")
+            np.testing.assert_array_equal(resp.levels["variant"][0][:it], got)
+    for bad in ([0.0, 1.0], [0.1, 0.0], [0.1, 2.0], [np.nan, 1.0]):
+        with pytest.raises(ss.SlimSellError):
+            ss.sched_load(np.concatenate([w, bad, np.zeros(6)]).astype(np.float32))
+    ss.sched_clear()
+    G.close()
