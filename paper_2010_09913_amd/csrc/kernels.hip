@@ -209,14 +209,23 @@ struct SelMax {
 #pragma unroll
     for (int t = 0; t < U; ++t)  // the 32-bit half of the chunk word holding bit c
       w[t] = gather_b32<STAGED>(r, st, c[t] >= 0 ? ((uint32_t)c[t] >> 5) << 2 : kOob);
-    int32_t x[U];
+    bool hit[U];
+    bool some = false;
 #pragma unroll
     for (int t = 0; t < U; ++t) {
-      const bool hit = c[t] >= 0 && ((w[t] >> (c[t] & 31)) & 1u);
-      x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+      hit[t] = c[t] >= 0 && ((w[t] >> (c[t] & 31)) & 1u);
+      some = some || hit[t];
     }
+    // Most blocks of the first and the late levels hit no frontier row: one
+    // wave-uniform test then spares the address unit U loads of v.
+    if (__any(some)) {
+      int32_t x[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
+      for (int t = 0; t < U; ++t)
+        x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit[t] ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+#pragma unroll
+      for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
+    }
     return acc;
   }
   __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
@@ -1056,6 +1065,9 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
 // ------------------------------------------------------- finalise kernel ---
 
 // Row order -> original IDs; infinity -> -1; 1-based parents -> 0-based.
+// One thread per original ID, so the outputs are written coalesced; the
+// row-order values are gathered.  (Scattering from row order instead writes
+// partial lines and measured more than twice as slow.)
 template <int SEMI>
 __global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* state,
                                 const int32_t* d, const float* rv, int32_t* dist, int32_t* parent,
