@@ -61,7 +61,10 @@ typedef enum {
  *   consecutive original IDs (stable on the ID), then relabelled to their
  *   sorted position; chunk i holds rows [64 i, 64 i + 64).
  *   col[cs[i] + 64 j + lane] is the relabelled ID of the j-th neighbour of row
- *   64 i + lane, or -1 where the row is shorter than the chunk (padding).
+ *   64 i + lane, or -1 where the row is shorter than the chunk (padding); a
+ *   row lists its neighbours by decreasing original ID, so a product that
+ *   keeps the largest ID (sel-max, and the DP transformation) may stop at the
+ *   first qualifying neighbour.
  *   The number of vertices is padded to a multiple of 64 with phantom rows
  *   (degree 0, never reachable).
  */
@@ -275,8 +278,11 @@ typedef struct {
  *                     1 = skip chunks whose rows are all final (SlimWork,
  *                     Section III-C);
  *                     2 = SlimWork plus row-level masking: inside a processed
- *                     chunk a row that is final issues no loads and the
- *                     column sweep stops at the longest row still live.
+ *                     chunk a row that is final issues no loads, the column
+ *                     sweep stops at the longest row still live, and under
+ *                     tropical, boolean and sel-max a row stops at its first
+ *                     frontier neighbour (its value is then final; sel-max
+ *                     rows list neighbours by decreasing original ID).
  *                     Results are identical in all three modes.
  *   split_len       : SlimChunk piece length in columns (Section III-D):
  *                     0 = chunks are never split, >0 = split chunks longer than

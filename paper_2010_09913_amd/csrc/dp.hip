@@ -12,8 +12,9 @@
 // per row, distance mod 3 (3 = unreached): a neighbour u of a vertex at
 // level k is at level k-1, k or k+1, which the code tells apart, so the
 // gathered array is n/4 bytes (1 MB for 4M vertices, resident in L2) instead
-// of 4n.  A hit then reads v[u] (original ID + 1).  Pieces of split chunks
-// combine with atomicMax, which is order-independent.
+// of 4n.  A hit then reads v[u] (original ID + 1).  A row lists its
+// neighbours by decreasing original ID, so a lane stops at its first hit.
+// Pieces of split chunks combine with atomicMax, which is order-independent.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -117,8 +118,9 @@ __global__ void dp_sweep_kernel(DpArgs a) {
 #pragma unroll
         for (int t = 0; t < U; ++t) best = x[t] > best ? x[t] : best;
         p += (int64_t)U * kC;
+        if (best > 0) break;  // rows list neighbours by decreasing ID: the first is the largest
       }
-      for (; j < hi; ++j) {
+      for (; best == 0 && j < hi; ++j) {
         const int32_t c1 = on ? __builtin_nontemporal_load(p) : -1;
         const uint32_t b1 = gather_b8<STAGED>(rc, sc, c1 >= 0 ? (uint32_t)c1 >> 2 : kOob);
         const bool hit = c1 >= 0 && ((b1 >> ((c1 & 3) * 2)) & 3u) == want;

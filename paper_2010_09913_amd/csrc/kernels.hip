@@ -49,6 +49,9 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 struct Tropical {
   static constexpr bool kSingleRoot = true;
   using Acc = int32_t;
+  // the first product term a row receives is its final value
+  static constexpr bool kFirstHitFinal = true;
+  __device__ static bool settled(Acc acc) { return acc != kInf; }
   __device__ static Acc identity() { return kInf; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
@@ -97,6 +100,9 @@ struct Tropical {
 struct Real {
   static constexpr bool kSingleRoot = true;
   using Acc = float;
+  // the first product term a row receives is its final value
+  static constexpr bool kFirstHitFinal = false;
+  __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0.0f; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
@@ -144,6 +150,9 @@ struct Real {
 struct Boolean {
   static constexpr bool kSingleRoot = true;
   using Acc = uint32_t;
+  // the first product term a row receives is its final value
+  static constexpr bool kFirstHitFinal = true;
+  __device__ static bool settled(Acc acc) { return acc != 0u; }
   __device__ static Acc identity() { return 0u; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
@@ -195,6 +204,9 @@ struct Boolean {
 struct SelMax {
   static constexpr bool kSingleRoot = true;
   using Acc = int32_t;
+  // the first product term a row receives is its final value
+  static constexpr bool kFirstHitFinal = true;
+  __device__ static bool settled(Acc acc) { return acc != 0; }
   __device__ static Acc identity() { return 0; }
   __device__ static Rsrc rsrc(const LevelArgs& a) {
     return make_rsrc(a.vin, (uint32_t)(a.n_pad / kC) * 8u);
@@ -264,6 +276,9 @@ struct SelMax {
 struct Batch {
   static constexpr bool kSingleRoot = false;
   using Acc = unsigned long long;
+  // the first product term a row receives is its final value
+  static constexpr bool kFirstHitFinal = false;
+  __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0ull; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 8u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) {
@@ -305,7 +320,12 @@ struct Batch {
 
 // Sweep `ncols` columns of one chunk for this lane's row, U columns at a time:
 // U independent streaming loads of `col`, then the U gathers of the block.  A
-// lane that is off (its row is final) issues no loads at all.
+// lane that is off (its row is final) issues no loads at all.  Where the
+// first product term a row receives is already its final value (tropical,
+// boolean, and sel-max, whose rows list their neighbours by decreasing
+// original ID), the lane stops after the block that produced it (SlimWork
+// mode 2; modes 0 and 1 compute every term); `cols` receives the columns the
+// lane loaded.
 //
 // VAL (the Sell-C-sigma comparator of Section II-C): a second stream, val,
 // runs beside col and decides whether a cell is an edge (1) or padding (0);
@@ -313,11 +333,14 @@ struct Batch {
 template <class S, int U, bool STAGED, bool VAL = false>
 __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Stage st,
                                                  const int32_t* __restrict__ p, int32_t ncols,
-                                                 bool on) {
+                                                 bool on, int32_t& cols) {
   typename S::Acc acc = S::identity();
+  cols = 0;
   if (!on) return acc;
   const int32_t* __restrict__ pv = VAL ? a.val + (p - a.col) : nullptr;
+  const bool stop = a.slimwork >= 2;  // modes 0 and 1 compute every term
   int32_t j = 0;
+  bool go = true;
   if (ncols >= 2 * U) {
     // Software pipeline: the next block's col (and val) loads are in flight
     // while this block's gathers (which depend on its col values) are
@@ -342,6 +365,10 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
       acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      if (S::kFirstHitFinal && stop && S::settled(acc)) {
+        go = false;
+        break;
+      }
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         c[t] = nc[t];
@@ -350,35 +377,52 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
       p += (int64_t)U * kC;
       if (VAL) pv += (int64_t)U * kC;
     }
-    if (VAL) {
+    if (go) {
+      if (VAL) {
 #pragma unroll
-      for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+        for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+      }
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      go = !(S::kFirstHitFinal && stop && S::settled(acc));
+      cols = j;
+    } else {
+      cols = j + U;  // the prefetched block was loaded too
     }
-    acc = S::template block<U, STAGED>(a, r, st, c, acc);
   }
-  for (; j + U <= ncols; j += U) {
-    int32_t c[U];
+  if (go) {
+    for (; j + U <= ncols; j += U) {
+      int32_t c[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
-    if (VAL) {
-      int32_t w[U];
+      for (int t = 0; t < U; ++t) c[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+      if (VAL) {
+        int32_t w[U];
 #pragma unroll
-      for (int t = 0; t < U; ++t) w[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+        for (int t = 0; t < U; ++t) w[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
 #pragma unroll
-      for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
-      pv += (int64_t)U * kC;
+        for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
+        pv += (int64_t)U * kC;
+      }
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      p += (int64_t)U * kC;
+      cols = j + U;
+      if (S::kFirstHitFinal && stop && S::settled(acc)) {
+        go = false;
+        break;
+      }
     }
-    acc = S::template block<U, STAGED>(a, r, st, c, acc);
-    p += (int64_t)U * kC;
   }
-  for (; j < ncols; ++j) {
-    int32_t c[1] = {__builtin_nontemporal_load(p)};
-    if (VAL) {
-      c[0] = __builtin_nontemporal_load(pv) ? c[0] : -1;
-      pv += kC;
+  if (go) {
+    for (; j < ncols; ++j) {
+      int32_t c[1] = {__builtin_nontemporal_load(p)};
+      if (VAL) {
+        c[0] = __builtin_nontemporal_load(pv) ? c[0] : -1;
+        pv += kC;
+      }
+      acc = S::template block<1, STAGED>(a, r, st, c, acc);
+      p += kC;
+      cols = j + 1;
+      if (S::kFirstHitFinal && stop && S::settled(acc)) break;
     }
-    acc = S::template block<1, STAGED>(a, r, st, c, acc);
-    p += kC;
   }
   return acc;
 }
@@ -429,8 +473,9 @@ __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uin
 
 // One BFS level.  slimwork: 0 = every row of every chunk is computed;
 // 1 = chunks whose rows are all final are skipped (Section III-C);
-// 2 = additionally a lane whose row is final issues no loads and the sweep
-// stops at the longest row that is still live.
+// 2 = additionally a lane whose row is final issues no loads, the sweep
+// stops at the longest row that is still live, and a row whose value became
+// final stops its scan.
 // The work of one level for one workgroup: stage the LDS prefix, sweep the
 // work units assigned to this workgroup's wavefronts, post-process, count.
 template <class S, int U, bool STAGED, bool VAL = false>
@@ -477,9 +522,10 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
         hi = lim < j1 ? lim : j1;
       }
       const int32_t ncols = hi > j0 ? hi - j0 : 0;
-      n_cols += (uint64_t)ncols;
       const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
-      typename S::Acc acc = sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on);
+      int32_t lane_cols;
+      typename S::Acc acc = sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on, lane_cols);
+      n_cols += (uint64_t)wave_max(lane_cols);  // columns the wavefront streamed
       const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
         found += finish_rows<S>(a, c, row, acc, lane, fdeg);

@@ -207,6 +207,8 @@ int build_layout(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, i
     for (int32_t v = 0; v < n; ++v) L->entries += deg[v];
 
     // ---- 5. column-major fill with the -1 padding marker -------------------
+    // A row lists its neighbours by decreasing original ID, so a scan that
+    // stops at its first frontier neighbour has found the largest one.
     L->col.assign((size_t)L->cells, -1);
     const int32_t* perm = L->perm.data();
     parallel_dynamic(nc, 64, [&](int64_t cb, int64_t ce) {
@@ -216,7 +218,8 @@ int build_layout(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, i
           int32_t v = L->v[i * kC + lane] - 1;
           if (v < 0) continue;
           const int32_t* nb = adj.data() + rp[v];
-          for (int32_t j = 0; j < deg[v]; ++j) base[(int64_t)j * kC + lane] = perm[nb[j]];
+          const int32_t d = deg[v];
+          for (int32_t j = 0; j < d; ++j) base[(int64_t)j * kC + lane] = perm[nb[d - 1 - j]];
         }
       }
     });

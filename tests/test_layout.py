@@ -53,6 +53,14 @@ def test_layout_invariants(kind, sigma):
     key = lambda a: np.sort(a[:, 0].astype(np.int64) * n_pad + a[:, 1])
     np.testing.assert_array_equal(key(stored), key(want))
     assert np.all((L.col >= -1) & (L.col < n_pad))
+    # each row lists its neighbours by strictly decreasing original ID (the
+    # sel-max scan stops at the first frontier neighbour)
+    for i in range(0, L.n_chunks, max(1, L.n_chunks // 40)):
+        blk = L.col[L.cs[i]:L.cs[i + 1]].reshape(-1, C)
+        for lane in range(C):
+            nb = blk[:, lane]
+            ids = L.v[nb[nb >= 0]] - 1
+            assert np.all(np.diff(ids) < 0)
     # L2: E + P cells, cs is the prefix of C * cl
     assert L.entries == g.entries
     assert L.cells == C * int(L.cl.sum()) == L.cs[-1]
