@@ -447,12 +447,39 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   return v;
 }
 
-// Flush one wavefront's tallies into the statistics and schedule counters.
+// Flush the tallies of one workgroup into the statistics and schedule
+// counters: every wavefront adds its tallies in LDS, then one thread adds the
+// workgroup's totals to its slot (and sets the level's "found" tag), so a
+// level issues a few global atomics per workgroup instead of per wavefront.
+// Every thread of the workgroup must call it.  Without counters it only sets
+// the tag, with no workgroup barrier.
 __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uint32_t found,
                                                uint32_t n_chunks, uint64_t n_cells,
                                                int32_t max_cl, uint64_t fdeg_lane) {
+  __shared__ unsigned long long tally[kCountFields];  // found, chunks, cells, max cl, fdeg
+  if (!a.count_stats && !a.ring_ctr) {
+    // nothing is counted (the condition is the same in every thread): only
+    // the level's "found" tag, from each wavefront that found rows
+    if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+    return;
+  }
   const uint64_t fdeg = wave_sum64(fdeg_lane);
-  if (lane != 0 || !(found | n_chunks | n_cells | fdeg)) return;
+  if (threadIdx.x < kCountFields) tally[threadIdx.x] = 0ull;
+  __syncthreads();
+  if (lane == 0) {
+    if (found) atomicAdd(&tally[0], (unsigned long long)found);
+    if (n_chunks) {
+      atomicAdd(&tally[1], (unsigned long long)n_chunks);
+      atomicMax(&tally[3], (unsigned long long)max_cl);
+    }
+    if (n_cells) atomicAdd(&tally[2], (unsigned long long)n_cells);
+    if (fdeg) atomicAdd(&tally[4], (unsigned long long)fdeg);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const unsigned long long t[kCountFields] = {tally[0], tally[1], tally[2], tally[3], tally[4]};
+  if (t[0]) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
+  if (!(t[0] | t[1] | t[2] | t[4])) return;
   unsigned long long* dst[2] = {nullptr, nullptr};
   const int slot = blockIdx.x % kCountSlots;
   if (a.count_stats)
@@ -461,13 +488,13 @@ __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uin
     dst[1] = a.ring_ctr + ((int64_t)(a.level % kRing) * kCountSlots + slot) * kCountFields;
   for (unsigned long long* ctr : dst) {
     if (!ctr) continue;
-    if (found) atomicAdd(&ctr[0], (unsigned long long)found);
-    if (n_chunks) {
-      atomicAdd(&ctr[1], (unsigned long long)n_chunks);
-      atomicMax(&ctr[3], (unsigned long long)max_cl);
+    if (t[0]) atomicAdd(&ctr[0], t[0]);
+    if (t[1]) {
+      atomicAdd(&ctr[1], t[1]);
+      atomicMax(&ctr[3], t[3]);
     }
-    if (n_cells) atomicAdd(&ctr[2], (unsigned long long)n_cells);
-    if (fdeg) atomicAdd(&ctr[4], (unsigned long long)fdeg);
+    if (t[2]) atomicAdd(&ctr[2], t[2]);
+    if (t[4]) atomicAdd(&ctr[4], t[4]);
   }
 }
 
@@ -547,7 +574,6 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       }
     }
   }
-  if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
   flush_counters(a, lane, found, n_chunks, n_cols * kC, max_cl, fdeg);
 }
 
@@ -754,7 +780,6 @@ __device__ __forceinline__ void push_post_body(const LevelArgs& a, int64_t gw, i
     }
     found += (uint32_t)__popcll(__ballot(fresh));
   }
-  if (lane == 0 && found) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
   flush_counters(a, lane, found, 0, 0, 0, fdeg);
 }
 
@@ -813,6 +838,7 @@ struct SchedArgs {
 struct SchedShared {
   float x[kFeatures], h1[32], h2[32], out[kVariants];
   float near[64];  // per-thread nearest squared anchor distance (first 64 threads)
+  unsigned long long cnt[kCountSlots][2];  // level k-1's found / frontier-degree slots
   double sums[3];
   float mf, mu;
   int32_t v, stop;
@@ -825,15 +851,22 @@ struct SchedShared {
 // workgroup, so all workgroups that call it with the same counters agree.
 __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh, bool writer) {
   const int t = threadIdx.x;
+  // Level k-1's counters: written by earlier kernels (or, in the persistent
+  // form, before the grid barrier, whose acquire makes them visible), so
+  // plain loads see them.  Sixteen lanes load one slot each, all in flight
+  // at once; the sums are formed in a fixed order, identically everywhere.
+  if (t < kCountSlots) {
+    const unsigned long long* c =
+        s.ring_ctr + ((int64_t)((k - 1) % kRing) * kCountSlots + t) * kCountFields;
+    sh.cnt[t][0] = c[0];
+    sh.cnt[t][1] = c[4];
+  }
+  __syncthreads();
   if (t == 0) {
     double nf = 0.0, mf = 0.0;
-    const unsigned long long* c =
-        s.ring_ctr + (int64_t)((k - 1) % kRing) * kCountSlots * kCountFields;
     for (int q = 0; q < kCountSlots; ++q) {
-      nf += (double)__hip_atomic_load(&c[q * kCountFields + 0], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-      mf += (double)__hip_atomic_load(&c[q * kCountFields + 4], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+      nf += (double)sh.cnt[q][0];
+      mf += (double)sh.cnt[q][1];
     }
     sh.stop = (k > 1 && nf == 0.0) ? 1 : 0;  // the previous level found nothing
     if (k > 1) {
