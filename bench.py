@@ -137,6 +137,17 @@ def profile_summary(args) -> int:
     return 0
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -274,6 +285,38 @@ def bench_sell(ss, e, roots, torch) -> dict:
     return out
 
 
+def bench_scale20(ss, graphgen, torch) -> dict:
+    """R-MAT scale 20, sigma = 2^14, 16 roots one at a time: GTEPS per
+    semiring, and the per-level shape of sel-max with and without SlimWork
+    (active cells and time per level, one root)."""
+    e = graphgen.rmat(20, 16, seed=1)
+    roots = graphgen.pick_roots(e, 16, seed=1001)
+    G = ss.Graph.from_edgelist(e, sigma=1 << 14)
+    deg = torch.from_numpy(G.degrees().astype(np.int64)).cuda()
+    out = {}
+    for semi in ("tropical", "real", "boolean", "selmax"):
+        G.bfs(roots, semi)
+        r = G.bfs(roots, semi, timing="bfs")
+        torch.cuda.synchronize()
+        m_cc = ((r.dist >= 0).to(torch.int64) * deg[None, :]).sum(dim=1).cpu().numpy() / 2
+        teps = m_cc / (r.runs["bfs_ms"] * 1e-3)
+        out[semi] = {"gteps_hmean": round(float(len(teps) / np.sum(1.0 / teps) / 1e9), 3),
+                     "mean_bfs_ms": round(float(np.mean(r.runs["bfs_ms"])), 4)}
+        log(f"scale 20 {semi}: {out[semi]}")
+    shape = {}
+    for sw in (0, 1, 2):
+        G.bfs(roots[:1], "selmax", slimwork=sw)
+        r = G.bfs(roots[:1], "selmax", slimwork=sw, level_cap=32, timing=True)
+        it = int(r.iterations[0])
+        shape[f"slimwork_{sw}"] = {
+            "active_cells": r.levels["active_cells"][0][:it].tolist(),
+            "level_ms": [round(float(x), 4) for x in r.levels["ms"][0][:it]],
+            "bfs_ms": round(float(r.runs["bfs_ms"][0]), 4)}
+    out["selmax_levels_root0"] = shape
+    G.close()
+    return out
+
+
 def bench_dp(G, roots, torch) -> dict:
     """Mean BFS time per root without and with parents: sel-max yields them from
     the product, the other semirings by the DP transformation after the BFS
@@ -329,6 +372,15 @@ def bench_batched(ss, graphgen, torch) -> dict:
         R[i, :len(rr)] = rr
     Gm.bfs_batch(R)
     t_many = _events_ms(torch, lambda: Gm.bfs_batch(R))
+    Gm.bfs_batch(R, persistent=True)
+    t_many_p = _events_ms(torch, lambda: Gm.bfs_batch(R, persistent=True))
+    t = time.perf_counter()
+    at = Gm.autotune(R, batched=True, repeats=1, force=True)
+    tune_s = time.perf_counter() - t
+    Gm.bfs_batch(R)
+    t_many_t = _events_ms(torch, lambda: Gm.bfs_batch(R))
+    Gm.bfs_batch(R, persistent=True)
+    t_many_tp = _events_ms(torch, lambda: Gm.bfs_batch(R, persistent=True))
     dist, iters, _, _ = Gm.bfs_batch(R)
     ns, off = Gm.parts()
     degm = torch.from_numpy(Gm.degrees().astype(np.int64)).cuda()
@@ -338,10 +390,16 @@ def bench_batched(ss, graphgen, torch) -> dict:
         blk = dd[64 * off[i]: 64 * (off[i] + ns[i])].view(64, int(ns[i]))
         edges += float(((blk >= 0).to(torch.int64) * degm[off[i]:off[i] + ns[i]][None, :]).sum() // 2)
     Gm.close()
-    log(f"256 ER graphs: {t_many:.2f} ms, {iters} levels, build {build:.1f}s")
+    log(f"256 ER graphs: {t_many:.2f} ms (persistent {t_many_p:.2f}, autotuned {t_many_t:.2f} / "
+        f"{t_many_tp:.2f}), {iters} levels, build {build:.1f}s")
+    best = min(t_many, t_many_p, t_many_t, t_many_tp)
     out["er_256_graphs"] = {"vertices": int(ns.sum()), "roots": int((R >= 0).sum()),
                             "levels": int(iters), "batched_ms": round(t_many, 3),
-                            "gteps": round(edges / t_many / 1e6, 3),
+                            "persistent_ms": round(t_many_p, 3),
+                            "autotuned_ms": round(t_many_t, 3),
+                            "autotuned_persistent_ms": round(t_many_tp, 3),
+                            "tune": at["best"], "tune_s": round(tune_s, 1),
+                            "gteps": round(edges / best / 1e6, 3),
                             "build_s": round(build, 1)}
     return out
 
@@ -554,6 +612,8 @@ def main() -> int:
                                    "frac": round(se.get("frac", 0.0), 4)}
         Ge.close()
 
+    if not args.only_timed and not args.no_extra:
+        result["rmat_s20_sigma2^14"] = bench_scale20(ss, graphgen, torch)
     if not args.only_timed and not args.no_batch:
         result["batched"] = bench_batched(ss, graphgen, torch)
     if not args.only_timed and not args.no_learned:
@@ -580,6 +640,22 @@ def main() -> int:
             "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"{len(sample)} of the {len(roots)} roots: FIFO-queue BFS + max-ID parent "
                       f"pass (the sel-max outputs), 1 thread, {cpu_s:.1f}s total",
+        }
+        # the level-synchronous OpenMP oracle on all host threads (distances)
+        rates = []
+        t_all = time.perf_counter()
+        for r in sample:
+            t = time.perf_counter()
+            d = oracle.bfs_omp(g, int(r))
+            dt = time.perf_counter() - t
+            rates.append(oracle.component_edges(g, d) / dt)
+        rates = np.array(rates)
+        result["cpu_baseline_all_cores"] = {
+            "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
+            "unit": "GTEPS", "cores": oracle.threads(), "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"the same {len(sample)} roots: level-synchronous top-down OpenMP BFS "
+                      f"(distances), {time.perf_counter() - t_all:.1f}s total",
         }
     print(json.dumps(result), flush=True)
     return 0

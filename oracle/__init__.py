@@ -49,6 +49,8 @@ def _load():
         lib.oracle_bfs.restype = ctypes.c_int64
         lib.oracle_bfs_omp.argtypes = [i64p, i32p, ctypes.c_int32, ctypes.c_int32, i32p]
         lib.oracle_bfs_omp.restype = ctypes.c_int32
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int32
         lib.oracle_parents_max.argtypes = [i64p, i32p, ctypes.c_int32, ctypes.c_int32, i32p, i32p]
         lib.oracle_parents_max.restype = None
         lib.oracle_real_counts.argtypes = [i64p, i32p, ctypes.c_int32, ctypes.c_int32, i32p, f32p]
@@ -107,6 +109,11 @@ def bfs(g: CSR, root: int) -> np.ndarray:
     if r < 0:
         raise ValueError("oracle_bfs failed")
     return dist
+
+
+def threads() -> int:
+    """Threads the OpenMP BFS uses."""
+    return int(_load().oracle_threads())
 
 
 def bfs_omp(g: CSR, root: int) -> np.ndarray:

@@ -46,6 +46,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static int cmp_i32(const void* a, const void* b) {
   int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
@@ -132,6 +135,15 @@ int64_t oracle_bfs(const int64_t* rowptr, const int32_t* adj, int32_t n, int32_t
  * parallelised with OpenMP.  It is the oracle's all-cores form, used only as a
  * CPU timing baseline.  Returns the number of levels swept.
  */
+/* Threads oracle_bfs_omp runs on (for the CPU baseline's core count). */
+int32_t oracle_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int32_t oracle_bfs_omp(const int64_t* rowptr, const int32_t* adj, int32_t n, int32_t root,
                        int32_t* dist) {
   for (int32_t v = 0; v < n; ++v) dist[v] = -1;
