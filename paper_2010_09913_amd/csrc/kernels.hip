@@ -610,29 +610,31 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, ui
                                              int* error) {
   __shared__ int ok;
   // Every wavefront's stores and atomics of the level must have reached L2
-  // before thread 0 writes L2 back and arrives: the workgroup barrier alone
-  // does not wait for them.
+  // before thread 0 releases them: the workgroup barrier alone does not wait
+  // for them.
   wait_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    __threadfence();  // release this workgroup's writes of the level
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (atomicAdd(&bar[0], 1u) == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (wall_clock64() - t0 > limit) {
-          atomicExch(error, 1);
-          ok = 0;
-          break;
-        }
+    // One release before arriving and one acquire after the wait: the
+    // arrival counter only grows (64-bit, cleared before the launch), so
+    // barrier e is passed once it reaches (e + 1) * nblocks, and polling it
+    // needs no ordering of its own.  (Full fences on both sides in every
+    // workgroup cost about three times as much per barrier.)
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(bar);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long arrived = atomicAdd(count, 1ull);
+    const unsigned long long target = (arrived / nblocks + 1ull) * nblocks;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (wall_clock64() - t0 > limit) {
+        atomicExch(error, 1);
+        ok = 0;
+        break;
       }
     }
-    __threadfence();  // acquire the other workgroups' writes
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
