@@ -540,7 +540,7 @@ static int run_levels(Graph& g, const RunPlan& p, int policy, LevelArgs a, void*
       pa.n_units = most;  // grid size only: the kernel uses its variant's units
       if ((lr = launch_sched_level(policy, p.waves, p.unroll, p.max_groups, pa, sl, st)))
         return lr;
-      if ((lr = launch_push(policy, a, st))) return lr;
+      if ((lr = launch_push(policy, a, g.max_cl > kPushLaneMax, st))) return lr;
     } else {
       if ((lr = launch_level(policy, p.waves, p.unroll, p.max_groups, a, st))) return lr;
     }

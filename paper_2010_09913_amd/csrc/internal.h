@@ -245,7 +245,11 @@ struct PersistentRun {
 };
 
 // Kernel launchers (kernels.hip).
-int launch_push(int semiring, const LevelArgs& a, void* stream);
+// Rows up to this degree are swept by one lane in a push level; longer rows
+// are cut into segments for the segments kernel, which a graph whose degrees
+// never exceed it does not need (segments = false).
+constexpr int kPushLaneMax = 32;
+int launch_push(int semiring, const LevelArgs& a, bool segments, void* stream);
 int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
                       const PersistentRun& r, void* stream);
 // One scheduled level: variant choice, then the pull variant or the push

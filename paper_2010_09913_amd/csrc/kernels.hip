@@ -668,7 +668,6 @@ __global__ void persistent_kernel(LevelArgs a, void* buf_a, void* buf_b, int32_t
 // kernel then post-processes the claimed rows.  Since A is symmetric, row u's
 // cells in the SlimSell layout are its neighbours.
 
-constexpr int kPushLaneMax = 32;    // rows up to this degree are swept by one lane
 constexpr int kPushSegment = 1024;  // longer rows are cut into segments of this many cells
 
 template <class S>
@@ -1287,12 +1286,12 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
   return check_launch("level_kernel");
 }
 
-int launch_push(int semiring, const LevelArgs& a, void* stream) {
+int launch_push(int semiring, const LevelArgs& a, bool segments, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   constexpr unsigned kGroups = 2048, kThreads = 256;
   switch (semiring) {
 #define SS_PUSH(S)                                                  \
-  push_segments_kernel<S><<<kGroups, kThreads, 0, st>>>(a);          \
+  if (segments) push_segments_kernel<S><<<kGroups, kThreads, 0, st>>>(a); \
   push_post_kernel<S><<<kGroups / 2, kThreads, 0, st>>>(a);          \
   break;
     case SS_TROPICAL: SS_PUSH(Tropical)
