@@ -114,7 +114,7 @@ RUN_FIELDS = ("iterations", "launches", "kernel_ms", "bfs_ms")
 @dataclass
 class BfsResult:
     dist: "object"             # torch int32 [num_roots, n] (device)
-    parent: "object | None"    # torch int32 [num_roots, n] (sel-max only)
+    parent: "object | None"    # torch int32 [num_roots, n] (sel-max, or any with dp=True)
     real_val: "object | None"  # torch float32 [num_roots, n] (real only)
     iterations: np.ndarray     # int32 [num_roots]
     levels: dict | None = None  # field -> array [num_roots, level_cap]
