@@ -83,7 +83,7 @@ static void release_graph(Graph* g) {
                   g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots,
                   g->ws.q[0],   g->ws.q[1], g->ws.qn,   g->ws.variant, g->ws.ring_ctr,
                   g->ws.sched_sums, g->ws.model, g->ws.sched_log, g->ws.bar, g->ws.pstatus,
-                  g->ws.segs,   g->ws.seg_n};
+                  g->ws.segs,   g->ws.seg_n, g->ws.summ};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* ev : g->ev_pool)
@@ -216,6 +216,13 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.pstatus, 4))) return rc;
   if ((rc = dalloc(&ws.any, kRing))) return rc;
   SS_HIP(hipMemset(ws.any, 0, sizeof(uint64_t) * kRing));
+  // frontier summaries (one bit per chunk, three buffers) where they are small
+  // enough to sit in LDS beside the staged prefix
+  const int64_t summ_words = (g.n_chunks + 31) / 32;
+  if (summ_words * 4 <= kSummMaxBytes) {
+    if ((rc = dalloc(&ws.summ, 3 * summ_words))) return rc;
+    ws.summ_words = (int32_t)summ_words;
+  }
   void* h = nullptr;
   hipError_t e = hipHostMalloc(&h, sizeof(uint64_t) * kRing,
                                hipHostMallocMapped | hipHostMallocCoherent);
@@ -276,6 +283,7 @@ struct RunPlan {
   int64_t max_groups = 0, cap = 0, lcap = 0, words_per_run = 0;
   bool timing = false, counting = false, persistent = false, sell = false;
   bool level_events = false;  // timing: events around every level launch too
+  bool summ = false;          // frontier summaries filter the gathers (plain single-root runs)
   int32_t slimwork = 2;
   int32_t schedule = 0;
   uint32_t lds_bytes = 0;
@@ -333,9 +341,18 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
                          : policy == kBatchSemiring ? g.n_pad * 8
                                                   : g.n_pad * 4;
     p->lds_bytes = (uint32_t)(std::min<int64_t>(used, (int64_t)g.tune.lds_kib * 1024) / 16 * 16);
+    // room for the summary word behind the prefix
+    const int64_t room = std::max<int64_t>(0, (int64_t)g.lds_dev - 16) / 16 * 16;
+    p->lds_bytes = (uint32_t)std::min<int64_t>(p->lds_bytes, room);
   }
   if (o->schedule < 0 || o->schedule > 3 + kVariants - 1)
     return set_error(SS_EINVAL, "schedule must be 0..6");
+  // Plain single-root runs keep one summary bit per chunk of each level's
+  // frontier and skip the gathers of chunks without frontier rows.  Push
+  // levels of a scheduled run do not maintain it, and the batched masks are
+  // not filtered.
+  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring &&
+            (int64_t)p->lds_bytes + 4 * (int64_t)g.ws.summ_words <= g.lds_dev;
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
   p->schedule = o->schedule;
   int rc = get_units(g, split, pack, &p->ul);
@@ -407,6 +424,8 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
   a.n_pad = (uint32_t)g.n_pad;
   a.slimwork = p.slimwork;
   a.lds_bytes = p.lds_bytes;
+  a.summ = p.summ ? g.ws.summ : nullptr;
+  a.summ_words = g.ws.summ_words;
   if (p.schedule) {
     a.variant = g.ws.variant;
     for (int v = 0; v < kPullVariants; ++v) {
@@ -767,6 +786,7 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
         lds < 0)
       lds = 0;
     g->lds_cap = std::min(lds, 64 * 1024);
+    g->lds_dev = lds;
   }
   g->n = L->n;
   g->n_pad = L->n_pad;
@@ -901,7 +921,7 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
   for (int32_t r = 0; r < num_roots; ++r) {
     const uint32_t run = next_run_id(g);
     if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[r]))) return rc;
-    rc = launch_init(s, g, g.ws, g.h_perm[roots[r]], st);
+    rc = launch_init(s, g, g.ws, g.h_perm[roots[r]], plan.summ, st);
     if (rc) return rc;
     if (plan.schedule && (rc = launch_sched_init(g, g.ws, g.h_perm[roots[r]], st))) return rc;
     LevelArgs a = base_args(g, plan, o, run, r);

@@ -91,6 +91,11 @@ struct Workspace {
   int32_t* seg_n = nullptr;             // [2] segment counts by level parity
   unsigned* bar = nullptr;              // [2] grid barrier of the persistent kernel
   int32_t* pstatus = nullptr;           // [4] persistent run: levels, error, level cap
+  // frontier summaries: one bit per chunk, set when a row of the chunk entered
+  // the frontier; three buffers of summ_words words (level k writes k mod 3,
+  // reads k - 1 mod 3 and clears k + 1 mod 3); nullptr when too large
+  uint32_t* summ = nullptr;
+  int32_t summ_words = 0;
   // host-mapped report ring written by the GPU: (tag << 1) | found
   volatile uint64_t* h_report = nullptr;
   uint64_t* d_report = nullptr;  // device view of h_report
@@ -159,6 +164,7 @@ struct Graph {
   uint32_t run_id = 0;
   ss_tune tune{256, 16, 8, 512, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
   int32_t lds_cap = 0;                // largest LDS prefix the device allows, bytes
+  int32_t lds_dev = 0;                // dynamic LDS the device allows one workgroup, bytes
   std::mutex mu;
 };
 
@@ -204,10 +210,20 @@ struct LevelArgs {
   uint32_t run_id;
   uint32_t n_pad;    // rows (multiple of 64)
   uint32_t lds_bytes;  // prefix of the gathered vector staged in LDS (0 = none)
+  uint32_t* summ;      // frontier summaries (Workspace::summ) or nullptr: no gather filter
+  int32_t summ_words;
   int32_t level;     // k >= 1
   int32_t slimwork;
   int32_t count_stats;
 };
+
+// Dynamic LDS of a level launch: the staged prefix plus the frontier summary
+// (or, with a prefix but no summary, one all-ones summary word).
+inline uint32_t level_lds(const LevelArgs& a) {
+  if (a.summ) return a.lds_bytes + (uint32_t)a.summ_words * 4u;
+  return a.lds_bytes ? a.lds_bytes + 16u : 0u;
+}
+constexpr int64_t kSummMaxBytes = 32 * 1024;  // summaries above this size are not kept
 
 // Parameters of the schedule that stay fixed over one run.
 struct SchedLaunch {
@@ -261,7 +277,8 @@ int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
 int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t max_groups,
               const int32_t* dist, int32_t* parent, void* stream);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
-int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
+int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, bool summary,
+                void* stream);
 int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
                  void* stream);
 int launch_finalise(int semiring, const Graph& g, const Workspace& ws, int32_t* dist,

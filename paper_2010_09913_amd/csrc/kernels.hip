@@ -57,15 +57,17 @@ struct Tropical {
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
   // terms 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
   __device__ static const void* staged(const LevelArgs& a) { return a.state; }
-  template <int U, bool STAGED>
+  template <int U, bool STAGED, class F>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
-    int32_t y[U];
-#pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = (int32_t)gather_b32<STAGED>(r, st, off_of(c[t], 2));
+                              Acc acc, F&& issued) {
+    uint32_t y[U];
+    bool got[U];
+    gather_rows<U, STAGED, 1>(r, st, c, y, got, issued);
+    // a term left unread (its chunk had no frontier row) is infinity: a live
+    // row has no neighbour closer than the previous level
 #pragma unroll
     for (int t = 0; t < U; ++t) {
-      const int32_t term = (c[t] >= 0 && y[t] < a.level) ? y[t] + 1 : kInf;
+      const int32_t term = (got[t] && (int32_t)y[t] < a.level) ? (int32_t)y[t] + 1 : kInf;
       acc = term < acc ? term : acc;
     }
     return acc;
@@ -85,9 +87,8 @@ struct Tropical {
     return a.state[row] == level;
   }
   // f_k^row = min(f_{k-1}^row, acc): the zero diagonal of A' keeps the old value
-  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    const int32_t own = a.state[row];
-    const bool fresh = (own == kInf) && (acc != kInf);
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool live) {
+    const bool fresh = live && (acc != kInf);  // live: own value still infinity
     if (fresh) a.state[row] = acc;
     return fresh;
   }
@@ -107,15 +108,14 @@ struct Real {
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED>
+  template <int U, bool STAGED, class F>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
-    float y[U];
+                              Acc acc, F&& issued) {
+    uint32_t y[U];
+    bool got[U];
+    gather_rows<U, STAGED, 1>(r, st, c, y, got, issued);  // unread terms are 0.0f
 #pragma unroll
-    for (int t = 0; t < U; ++t)
-      y[t] = __int_as_float((int32_t)gather_b32<STAGED>(r, st, off_of(c[t], 2)));
-#pragma unroll
-    for (int t = 0; t < U; ++t) acc += y[t];
+    for (int t = 0; t < U; ++t) acc += __uint_as_float(y[t]);
     return acc;
   }
   __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
@@ -132,9 +132,8 @@ struct Real {
   __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
     return a.d[row] == level;
   }
-  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    const uint8_t gg = a.g[row];
-    const bool fresh = (acc * (float)gg) != 0.0f;
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool live) {
+    const bool fresh = live && acc != 0.0f;  // x_k (.) g_k != 0, live: g_k = 1
     static_cast<float*>(a.vout)[row] = fresh ? 1.0f : 0.0f;
     if (fresh) {
       a.d[row] = a.level;
@@ -157,12 +156,12 @@ struct Boolean {
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED>
+  template <int U, bool STAGED, class F>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, F&& issued) {
     uint32_t y[U];
-#pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = gather_b8<STAGED>(r, st, off_of(c[t], 0));
+    bool got[U];
+    gather_rows<U, STAGED, 0>(r, st, c, y, got, issued);  // unread terms are 0
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -181,8 +180,8 @@ struct Boolean {
   __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
     return a.d[row] == level;
   }
-  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    const bool fresh = (acc != 0u) && (a.g[row] != 0);
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool live) {
+    const bool fresh = (acc != 0u) && live;  // live: g_k = 1
     static_cast<uint8_t*>(a.vout)[row] = fresh ? 1 : 0;
     if (fresh) {
       a.d[row] = a.level;
@@ -213,14 +212,13 @@ struct SelMax {
   }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED>
+  template <int U, bool STAGED, class F>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, F&& issued) {
     const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
-    uint32_t w[U];
-#pragma unroll
-    for (int t = 0; t < U; ++t)  // the 32-bit half of the chunk word holding bit c
-      w[t] = gather_b32<STAGED>(r, st, c[t] >= 0 ? ((uint32_t)c[t] >> 5) << 2 : kOob);
+    uint32_t w[U];  // the 32-bit half of the chunk word holding bit c (0 if unread)
+    bool got[U];
+    gather_rows<U, STAGED, 2>(r, st, c, w, got, issued);
     bool hit[U];
     bool some = false;
 #pragma unroll
@@ -255,8 +253,8 @@ struct SelMax {
   __device__ static bool entered(const LevelArgs& a, int32_t row, int32_t level) {
     return a.d[row] == level;
   }
-  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
-    const bool fresh = (a.state[row] == 0) && (acc != 0);
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool live) {
+    const bool fresh = live && (acc != 0);  // live: p still 0
     if (fresh) {
       a.state[row] = acc;
       a.d[row] = a.level;
@@ -286,12 +284,13 @@ struct Batch {
     return (a.vis[row] & full) != full;
   }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED>
+  template <int U, bool STAGED, class F>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, F&& issued) {
     Acc y[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, off_of(c[t], 3));
+    issued();
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -300,7 +299,7 @@ struct Batch {
     keep((int32_t)atomicOr(&a.acc64[row], v));
   }
   __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc64[row], 0ull); }
-  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc) {
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool) {
     const Acc seen = a.vis[row];
     Acc fresh = acc & ~seen & a.full[row / kC];
     static_cast<Acc*>(a.vout)[row] = fresh;
@@ -344,8 +343,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
   if (ncols >= 2 * U) {
     // Software pipeline: the next block's col (and val) loads are in flight
     // while this block's gathers (which depend on its col values) are
-    // served, so a block costs one memory latency instead of two.  (A second
-    // block of depth measured no faster and costs U more registers.)
+    // served, so a block costs one memory latency instead of two.
     int32_t c[U], w[U], nc[U], nw[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
@@ -355,16 +353,18 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
     p += (int64_t)U * kC;
     if (VAL) pv += (int64_t)U * kC;
     for (j = U; j + U <= ncols; j += U) {
-#pragma unroll
-      for (int t = 0; t < U; ++t) {
-        nc[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
-        if (VAL) nw[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
-      }
       if (VAL) {
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      // the next block's loads are issued right behind this block's gathers
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, [&] {
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+          nc[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+          if (VAL) nw[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+        }
+      });
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
         go = false;
         break;
@@ -382,7 +382,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
       go = !(S::kFirstHitFinal && stop && S::settled(acc));
       cols = j;
     } else {
@@ -402,7 +402,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
         pv += (int64_t)U * kC;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
       p += (int64_t)U * kC;
       cols = j + U;
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
@@ -411,21 +411,26 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
       }
     }
   }
-  if (go) {
-    for (; j < ncols; ++j) {
-      int32_t c[1] = {__builtin_nontemporal_load(p)};
-      if (VAL) {
-        c[0] = __builtin_nontemporal_load(pv) ? c[0] : -1;
-        pv += kC;
-      }
-      acc = S::template block<1, STAGED>(a, r, st, c, acc);
-      p += kC;
-      cols = j + 1;
-      if (S::kFirstHitFinal && stop && S::settled(acc)) break;
+  if (go && j < ncols) {
+    // the ragged tail of fewer than U columns as one block: the columns past
+    // the end repeat the last address (a cache hit) and are masked to padding,
+    // so the tail costs one load round trip rather than one per column
+    const int32_t rem = ncols - j;
+    int32_t c[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int64_t o = (int64_t)(t < rem ? t : rem - 1) * kC;
+      c[t] = __builtin_nontemporal_load(p + o);
+      if (VAL) c[t] = __builtin_nontemporal_load(pv + o) ? c[t] : -1;
     }
+#pragma unroll
+    for (int t = 0; t < U; ++t) c[t] = t < rem ? c[t] : -1;
+    acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
+    cols = ncols;
   }
   return acc;
 }
+
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
@@ -433,10 +438,13 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane
 // and adds their degrees to `fdeg`.
 template <class S>
 __device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chunk, int32_t row,
-                                                typename S::Acc acc, int lane, uint64_t& fdeg) {
-  const bool fresh = S::post(a, row, acc);
+                                                typename S::Acc acc, bool live, int lane,
+                                                uint64_t& fdeg) {
+  const bool fresh = S::post(a, row, acc, live);
   const uint64_t mask = __ballot(fresh);
   S::publish(a, chunk, mask, lane);
+  if (a.summ && lane == 0 && mask)  // the chunk has a frontier row for the next level
+    atomicOr(a.summ + (int64_t)(a.level % 3) * a.summ_words + (chunk >> 5), 1u << (chunk & 31));
   if (fresh) fdeg += (uint64_t)a.deg[row];
   return (uint32_t)__popcll(mask);
 }
@@ -514,11 +522,27 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   const int waves = blockDim.x / kC;
   const Rsrc rs = S::rsrc(a);
   Stage st{lds_stage, 0u};
+  if (a.summ) {
+    // clear the summary the next level writes (read by the level before this one)
+    uint32_t* next = a.summ + (int64_t)((a.level + 1) % 3) * a.summ_words;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.summ_words;
+         i += (int64_t)gridDim.x * blockDim.x)
+      next[i] = 0u;
+  }
   if (STAGED) {
-    // copy the vector's first a.lds_bytes (a multiple of 16) into LDS
+    // copy the vector's first a.lds_bytes (a multiple of 16) into LDS, then
+    // the previous level's frontier summary behind it
     const uint4* src = static_cast<const uint4*>(S::staged(a));
     uint4* dst = reinterpret_cast<uint4*>(lds_stage);
     for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+    uint32_t* sd = reinterpret_cast<uint32_t*>(lds_stage + a.lds_bytes);
+    if (a.summ) {
+      const uint32_t* prev = a.summ + (int64_t)((a.level - 1) % 3) * a.summ_words;
+      for (int32_t i = threadIdx.x; i < a.summ_words; i += blockDim.x) sd[i] = prev[i];
+      st.summ_mask = ~0u;
+    } else if (threadIdx.x == 0) {
+      sd[0] = ~0u;  // no summary: every chunk counts as holding frontier rows
+    }
     __syncthreads();
     st.bytes = a.lds_bytes;
   }
@@ -527,41 +551,50 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   uint64_t n_cols = 0, fdeg = 0;
   int32_t max_cl = 0;
 
-  for (int64_t u = (int64_t)blockIdx.x * waves + wave; u < n_units;
-       u += (int64_t)gridDim.x * waves) {
-    const Unit w = units[u];
+  const int64_t stride = (int64_t)gridDim.x * waves;
+  int64_t u = (int64_t)blockIdx.x * waves + wave;
+  Unit w{0, 0, 0, 0};
+  if (u < n_units) w = units[u];
+  for (; u < n_units; u += stride) {
+    // the next unit's descriptor is read while this one is swept
+    Unit wn = w;
+    if (u + stride < n_units) wn = units[u + stride];
     const bool piece = (w.c1 == w.c0 + 1);
     for (int32_t c = w.c0; c < w.c1; ++c) {
       const int32_t row = c * kC + lane;
+      // the chunk's extent and the row's degree are read together with its
+      // state, so the column stream starts one memory latency after the unit
+      const int32_t len = a.cl[c];
+      const int64_t start = a.cs[c];
+      const int32_t dg = a.deg[row];
       const bool live = S::live(a, row);
       if (a.slimwork && !__any(live)) continue;  // whole chunk final
-      int32_t j0 = 0, j1 = a.cl[c];
+      int32_t j0 = 0, j1 = len;
       if (piece) { j0 = w.j0; j1 = w.j1; }
       if (j0 == 0) {
         ++n_chunks;
-        const int32_t len = a.cl[c];
         max_cl = len > max_cl ? len : max_cl;
       }
       const bool on = (a.slimwork >= 2) ? live : true;
       int32_t hi = j1;
       if (a.slimwork >= 2) {
-        const int32_t lim = wave_max(on ? a.deg[row] : 0);
+        const int32_t lim = wave_max(on ? dg : 0);
         hi = lim < j1 ? lim : j1;
       }
       const int32_t ncols = hi > j0 ? hi - j0 : 0;
-      const int32_t* p = a.col + a.cs[c] + (int64_t)j0 * kC + lane;
+      const int32_t* p = a.col + start + (int64_t)j0 * kC + lane;
       int32_t lane_cols;
       typename S::Acc acc = sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on, lane_cols);
       n_cols += (uint64_t)wave_max(lane_cols);  // columns the wavefront streamed
       const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
-        found += finish_rows<S>(a, c, row, acc, lane, fdeg);
+        found += finish_rows<S>(a, c, row, acc, live, lane, fdeg);
       } else {
         // SlimChunk: combine this piece, the last one to arrive post-processes.
         // Pieces exchange data only through device-scope atomics: each piece's
         // combine has completed before its arrival is counted, so the last
         // arrival's exchange sees every piece.
-        S::atomic_combine(a, row, acc);
+        if (acc != S::identity()) S::atomic_combine(a, row, acc);  // identity: no change
         wait_memory();
         int last = 0;
         if (lane == 0) last = (atomicAdd(&a.arrive[c], 1) == npieces - 1);
@@ -569,10 +602,11 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
         if (last) {
           acc = S::take(a, row);
           if (lane == 0) a.arrive[c] = 0;
-          found += finish_rows<S>(a, c, row, acc, lane, fdeg);
+          found += finish_rows<S>(a, c, row, acc, live, lane, fdeg);
         }
       }
     }
+    w = wn;
   }
   flush_counters(a, lane, found, n_chunks, n_cols * kC, max_cl, fdeg);
 }
@@ -773,7 +807,7 @@ __device__ __forceinline__ void push_post_body(const LevelArgs& a, int64_t gw, i
     const int32_t w = mine ? a.q_out[i] : 0;
     bool fresh = false;
     if (mine) {
-      fresh = S::post(a, w, S::take(a, w));
+      fresh = S::post(a, w, S::take(a, w), S::live(a, w));
       if (fresh) {
         S::publish_one(a, w);
         fdeg += (uint64_t)a.deg[w];
@@ -1107,9 +1141,16 @@ __global__ void persistent_sched_kernel(LevelArgs a, SchedArgs s, void* buf_a, v
 template <int SEMI>
 __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const int32_t* v,
                             int32_t root_row, void* va, void* vb, int32_t* state, uint8_t* g,
-                            int32_t* d, float* rv, int32_t* acc, int32_t* arrive) {
+                            int32_t* d, float* rv, int32_t* acc, int32_t* arrive, uint32_t* summ,
+                            int32_t summ_words) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_chunks) arrive[r] = 0;
+  if (summ && r < summ_words) {
+    // level 0's frontier summary holds the root's chunk; level 1's starts empty
+    const int32_t rc = root_row / kC;
+    summ[r] = (r == rc >> 5) ? (1u << (rc & 31)) : 0u;
+    summ[summ_words + r] = 0u;
+  }
   if (r >= n_pad) return;
   // sel-max: one bitmap word per chunk is initialised below
   const bool root = (r == root_row);
@@ -1225,15 +1266,16 @@ static inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)((n + threads - 1) / threads);
 }
 
-int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row,
+int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, bool summary,
                 void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t work = g.n_pad > g.n_chunks ? g.n_pad : g.n_chunks;
   const unsigned blocks = blocks_for(work, 256);
+  uint32_t* summ = summary ? ws.summ : nullptr;
 #define SS_INIT(S)                                                                             \
   init_kernel<S><<<blocks, 256, 0, st>>>(g.n, g.n_pad, g.n_chunks, g.d_v, root_row, ws.vec_a, \
                                          ws.vec_b, ws.state, ws.g, ws.d, ws.rv, ws.acc,       \
-                                         ws.arrive)
+                                         ws.arrive, summ, ws.summ_words)
   switch (semiring) {
     case SS_TROPICAL: SS_INIT(SS_TROPICAL); break;
     case SS_REAL: SS_INIT(SS_REAL); break;
@@ -1248,7 +1290,7 @@ int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_
 template <class S, bool STAGED>
 static void launch_level_u(int waves, int unroll, unsigned grid, const LevelArgs& a,
                            hipStream_t st) {
-  const size_t lds = STAGED ? a.lds_bytes : 0;
+  const size_t lds = STAGED ? level_lds(a) : 0;
   if (a.val)  // the Sell-C-sigma comparator is built for one unroll depth
     level_kernel<S, 8, STAGED, true><<<grid, waves * kC, lds, st>>>(a);
   else if (unroll == 4)
@@ -1262,7 +1304,7 @@ static void launch_level_u(int waves, int unroll, unsigned grid, const LevelArgs
 template <class S>
 static void launch_level_t(int waves, int unroll, unsigned grid, const LevelArgs& a,
                            hipStream_t st) {
-  if (a.lds_bytes)
+  if (level_lds(a))
     launch_level_u<S, true>(waves, unroll, grid, a, st);
   else
     launch_level_u<S, false>(waves, unroll, grid, a, st);
@@ -1331,7 +1373,7 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
 template <class S, bool STAGED>
 static void launch_sched_level_u(int waves, int unroll, unsigned grid, const LevelArgs& a,
                                  const SchedArgs& sa, hipStream_t st) {
-  const size_t lds = STAGED ? a.lds_bytes : 0;
+  const size_t lds = STAGED ? level_lds(a) : 0;
   if (unroll == 4)
     sched_level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
   else if (unroll == 16)
@@ -1349,7 +1391,7 @@ int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
   const unsigned grid = (unsigned)groups;
   const SchedArgs sa = sched_args(p, a.level, a.run_id);
 #define SS_SL(S)                                                      \
-  if (a.lds_bytes)                                                    \
+  if (level_lds(a))                                                   \
     launch_sched_level_u<S, true>(waves, unroll, grid, a, sa, st);    \
   else                                                                \
     launch_sched_level_u<S, false>(waves, unroll, grid, a, sa, st);   \
@@ -1380,7 +1422,7 @@ constexpr int kPersistentWaves = 16;
 template <class S, bool STAGED>
 static int launch_persistent_u(int unroll, const LevelArgs& a, void* buf_a, void* buf_b,
                                const PersistentRun& r, hipStream_t st) {
-  const size_t lds = STAGED ? a.lds_bytes : 0;
+  const size_t lds = STAGED ? level_lds(a) : 0;
   const void* fn;
   if (r.sched) {
     if constexpr (S::kSingleRoot) {
@@ -1432,7 +1474,7 @@ int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a,
                       const PersistentRun& r, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
 #define SS_PERS(S)                                                                \
-  return a.lds_bytes ? launch_persistent_u<S, true>(unroll, a, buf_a, buf_b, r, st) \
+  return level_lds(a) ? launch_persistent_u<S, true>(unroll, a, buf_a, buf_b, r, st) \
                      : launch_persistent_u<S, false>(unroll, a, buf_a, buf_b, r, st);
   switch (semiring) {
     case SS_TROPICAL: SS_PERS(Tropical)
