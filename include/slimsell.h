@@ -271,6 +271,16 @@ typedef struct {
  * instead of 4.  Built on the device at first use (2 x 4 B per cell).  Same
  * results; single-root levels only (no schedule, no persistent launch). */
 #define SS_SELL_VAL 8
+/* Plain single-root runs under tropical, real and boolean record, per level,
+ * one bit per chunk that gained frontier rows (a frontier summary, 2 KiB per
+ * million vertices, kept where it is at most 32 KiB).  While few chunks hold
+ * frontier rows, the next level stages it in LDS and reads a term of the
+ * product from memory only when its row's chunk holds frontier rows; every
+ * other term is the semiring's identity for each row whose value can still
+ * change, so results are unchanged.  This flag turns the summary off (every
+ * term outside the staged prefix is read).  Sel-max runs, runs with a
+ * schedule and the batched SpMM never use it. */
+#define SS_NO_SUMMARY 32
 
 /*
  * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
@@ -307,7 +317,7 @@ typedef struct {
  *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
  *                     (eccentricity + 1; the last one discovers nothing).
  *   flags           : SS_STATS_TIME, SS_STATS_TIME_BFS, SS_STATS_COUNTERS,
- *                     SS_RUN_PERSISTENT, SS_SELL_VAL.
+ *                     SS_RUN_PERSISTENT, SS_SELL_VAL, SS_NO_SUMMARY.
  *   level_cap       : levels per root recorded in level_stats_out.
  *   level_stats_out : host ss_level_stats[num_roots * level_cap] or NULL;
  *                     entry [r * level_cap + k - 1] describes level k of root r.

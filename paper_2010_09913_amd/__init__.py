@@ -217,13 +217,14 @@ class Graph:
             waves_per_group: int = 0, schedule: int = 0, max_levels: int = 0, stream=None,
             level_cap: int = 0, timing: bool = False, counters: bool = None,
             persistent: bool = False, want_parent: bool = True, want_real: bool = True,
-            dp: bool = False, sell: bool = False, dist=None, parent=None,
-            real_val=None) -> BfsResult:
+            dp: bool = False, sell: bool = False, summary: bool = True, dist=None,
+            parent=None, real_val=None) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
         Sel-max returns parents (unless want_parent=False); dp=True gives the
         other semirings parents too, by the DP transformation after each BFS.
         sell=True runs the Sell-C-sigma comparator (a val array beside col).
+        summary=False turns off the frontier-summary filter of the gathers.
         level_cap > 0 records per-level statistics (fused counters unless
         counters=False); timing=True adds event timings per level and per root,
         timing="bfs" per root only.
@@ -260,7 +261,8 @@ class Graph:
                    _native.SS_STATS_TIME if timing else 0) | (
             _native.SS_STATS_COUNTERS if counters else 0) | (
             _native.SS_RUN_PERSISTENT if persistent else 0) | (
-            _native.SS_SELL_VAL if sell else 0)
+            _native.SS_SELL_VAL if sell else 0) | (
+            0 if summary else _native.SS_NO_SUMMARY)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * (nr * level_cap))()

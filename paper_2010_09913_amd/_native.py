@@ -85,6 +85,7 @@ SS_STATS_COUNTERS = 2
 SS_RUN_PERSISTENT = 4
 SS_SELL_VAL = 8
 SS_STATS_TIME_BFS = 16
+SS_NO_SUMMARY = 32
 
 
 class BfsOpts(ctypes.Structure):

@@ -319,7 +319,8 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   p->cap = (o->max_levels > 0) ? std::min<int64_t>(o->max_levels, default_cap) : default_cap;
   if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
   if (o->flags &
-      ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT | SS_SELL_VAL | SS_STATS_TIME_BFS))
+      ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT | SS_SELL_VAL | SS_STATS_TIME_BFS |
+        SS_NO_SUMMARY))
     return set_error(SS_EINVAL, "bad flags");
   p->persistent = (o->flags & SS_RUN_PERSISTENT) != 0;
   p->sell = (o->flags & SS_SELL_VAL) != 0;
@@ -341,17 +342,17 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
                          : policy == kBatchSemiring ? g.n_pad * 8
                                                   : g.n_pad * 4;
     p->lds_bytes = (uint32_t)(std::min<int64_t>(used, (int64_t)g.tune.lds_kib * 1024) / 16 * 16);
-    // room for the summary word behind the prefix
-    const int64_t room = std::max<int64_t>(0, (int64_t)g.lds_dev - 16) / 16 * 16;
-    p->lds_bytes = (uint32_t)std::min<int64_t>(p->lds_bytes, room);
   }
   if (o->schedule < 0 || o->schedule > 3 + kVariants - 1)
     return set_error(SS_EINVAL, "schedule must be 0..6");
-  // Plain single-root runs keep one summary bit per chunk of each level's
-  // frontier and skip the gathers of chunks without frontier rows.  Push
-  // levels of a scheduled run do not maintain it, and the batched masks are
-  // not filtered.
-  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring &&
+  // Plain single-root runs under tropical, real and boolean keep one summary
+  // bit per chunk of each level's frontier and skip the gathers of chunks
+  // without frontier rows.  Sel-max does not: its gathered bitmap is one bit
+  // per row, so the LDS prefix already serves most terms and the summary's
+  // upkeep costs more than it saves.  Push levels of a scheduled run do not
+  // maintain it, and the batched masks are not filtered.
+  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring && policy != SS_SELMAX &&
+            !(o->flags & SS_NO_SUMMARY) &&
             (int64_t)p->lds_bytes + 4 * (int64_t)g.ws.summ_words <= g.lds_dev;
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
   p->schedule = o->schedule;

@@ -36,10 +36,9 @@ __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)
 struct Stage {
   const uint8_t* lds;
   uint32_t bytes;  // 0 = nothing staged
-  // The frontier summary sits in LDS right behind the prefix (at byte
-  // `bytes`), one bit per 64-row chunk.  With summ_mask 0 it is a single
-  // all-ones word, so every term outside the prefix is read.
-  uint32_t summ_mask = 0u;
+  // filter: the frontier summary sits in LDS right behind the prefix (at
+  // byte `bytes`), one bit per 64-row chunk, and this level uses it
+  bool filter = false;
 };
 
 template <bool STAGED>
@@ -75,24 +74,42 @@ __device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint3
 // vector for each lane (c[t] = -1 is padding).  KIND 0: one byte per row;
 // 1: four bytes per row; 2: the 32-bit word of a one-bit-per-row bitmap that
 // holds row c.  A term is read from LDS when the staged prefix holds it.
-// With a frontier summary staged, a term outside the prefix is read from
-// memory only when its row's chunk had a row enter the frontier in the
-// previous level; otherwise it is left unread (got[t] false, y[t] 0).  If no
-// lane of the block needs memory, no load instruction is issued at all: this
-// is what makes levels with a small frontier cheap, since every other term
-// of the product is then the semiring's identity.
+// With the filter on, a term outside the prefix is read from memory only
+// when its row's chunk had a row enter the frontier in the previous level;
+// otherwise it is left unread (got[t] false, y[t] 0).  If no lane of the
+// block needs memory, no load instruction is issued at all: this is what
+// makes levels with a small frontier cheap, since every other term of the
+// product is then the semiring's identity.  The filter costs an LDS round
+// trip before the memory gathers, so levels whose frontier touches many
+// chunks run without it.
 template <int U, bool STAGED, int KIND>
 __device__ __forceinline__ uint32_t row_offset(int32_t c) {
   const uint32_t cu = (uint32_t)c;
   return c < 0 ? kOob : KIND == 0 ? cu : KIND == 1 ? (cu << 2) : ((cu >> 5) << 2);
 }
-//
-// `issued()` runs right after the memory gathers are issued: the caller's
-// next loads (the following block's columns) then sit behind them in the
-// in-order memory counter, and waiting for the gathers leaves those in flight.
-template <int U, bool STAGED, int KIND, class F>
+template <int U, bool STAGED, int KIND>
 __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)[U],
-                                            uint32_t (&y)[U], bool (&got)[U], F&& issued) {
+                                            uint32_t (&y)[U], bool (&got)[U]) {
+  if (!STAGED || !st.filter) {
+    // every term: LDS if the prefix holds it, else memory; both loads are
+    // issued without a branch (the LDS address is clamped and its value
+    // masked, the buffer load gets an out-of-range offset when LDS serves it)
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const uint32_t off = row_offset<U, STAGED, KIND>(c[t]);
+      const bool in = STAGED && off < st.bytes;
+      uint32_t l = 0u;
+      if (STAGED) {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : 0u));
+        l = !in ? 0u : KIND == 0 ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
+      }
+      const uint32_t o = in ? kOob : off;
+      y[t] = l | (KIND == 0 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o, 0, 0)
+                            : __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+      got[t] = c[t] >= 0;
+    }
+    return;
+  }
   uint32_t o[U];  // memory offset of the term, kOob when LDS serves it or it is skipped
   bool some = false;
 #pragma unroll
@@ -100,35 +117,29 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     const bool valid = c[t] >= 0;
     const uint32_t cu = valid ? (uint32_t)c[t] : 0u;
     const uint32_t off = row_offset<U, STAGED, KIND>(c[t]);
-    const bool in = STAGED && off < st.bytes;
-    y[t] = 0u;
-    uint32_t need = valid && !in ? 1u : 0u;
-    if (STAGED) {
-      // one LDS read per term: the staged element if the prefix holds it,
-      // else the summary word of its chunk (stored right behind the prefix)
-      const uint32_t sw = st.bytes + (((cu >> 11) & st.summ_mask) << 2);
-      const uint32_t v =
-          *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
-      y[t] = !in ? 0u : KIND == 0 ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
-      need &= v >> ((cu >> 6) & 31u);
-    }
-    o[t] = (need & 1u) ? off : kOob;
-    some = some || (need & 1u);
+    const bool in = off < st.bytes;
+    // one LDS read per term: the staged element if the prefix holds it,
+    // else the summary word of its chunk (stored right behind the prefix)
+    const uint32_t sw = st.bytes + ((cu >> 11) << 2);
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
+    y[t] = !in ? 0u : KIND == 0 ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
+    const uint32_t need = (valid && !in ? 1u : 0u) & (v >> ((cu >> 6) & 31u));
+    o[t] = need ? off : kOob;
+    some = some || need;
   }
   uint32_t g[U];
 #pragma unroll
   for (int t = 0; t < U; ++t) g[t] = 0u;
-  if (!STAGED || __any(some)) {
+  if (__any(some)) {
 #pragma unroll
     for (int t = 0; t < U; ++t)
       g[t] = KIND == 0 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o[t], 0, 0)
                        : __builtin_amdgcn_raw_buffer_load_b32(r, o[t], 0, 0);
   }
-  issued();
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     y[t] |= g[t];
-    got[t] = o[t] != kOob || (STAGED && row_offset<U, STAGED, KIND>(c[t]) < st.bytes);
+    got[t] = o[t] != kOob || row_offset<U, STAGED, KIND>(c[t]) < st.bytes;
   }
 }
 

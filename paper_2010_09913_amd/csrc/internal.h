@@ -217,11 +217,9 @@ struct LevelArgs {
   int32_t count_stats;
 };
 
-// Dynamic LDS of a level launch: the staged prefix plus the frontier summary
-// (or, with a prefix but no summary, one all-ones summary word).
+// Dynamic LDS of a level launch: the staged prefix plus the frontier summary.
 inline uint32_t level_lds(const LevelArgs& a) {
-  if (a.summ) return a.lds_bytes + (uint32_t)a.summ_words * 4u;
-  return a.lds_bytes ? a.lds_bytes + 16u : 0u;
+  return a.lds_bytes + (a.summ ? (uint32_t)a.summ_words * 4u : 0u);
 }
 constexpr int64_t kSummMaxBytes = 32 * 1024;  // summaries above this size are not kept
 

@@ -48,6 +48,9 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
   static constexpr bool kSingleRoot = true;
+  // frontier-summary filter at every density: with 4 bytes per row, terms
+  // outside the LDS prefix are most terms, and skipping some always pays
+  static constexpr int kFilterShift = 0;
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -57,12 +60,12 @@ struct Tropical {
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
   // terms 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
   __device__ static const void* staged(const LevelArgs& a) { return a.state; }
-  template <int U, bool STAGED, class F>
+  template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc, F&& issued) {
+                              Acc acc) {
     uint32_t y[U];
     bool got[U];
-    gather_rows<U, STAGED, 1>(r, st, c, y, got, issued);
+    gather_rows<U, STAGED, 1>(r, st, c, y, got);
     // a term left unread (its chunk had no frontier row) is infinity: a live
     // row has no neighbour closer than the previous level
 #pragma unroll
@@ -100,6 +103,7 @@ struct Tropical {
 // exact in fp32.
 struct Real {
   static constexpr bool kSingleRoot = true;
+  static constexpr int kFilterShift = 0;  // filter at every density (as tropical)
   using Acc = float;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = false;
@@ -108,12 +112,12 @@ struct Real {
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED, class F>
+  template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc, F&& issued) {
+                              Acc acc) {
     uint32_t y[U];
     bool got[U];
-    gather_rows<U, STAGED, 1>(r, st, c, y, got, issued);  // unread terms are 0.0f
+    gather_rows<U, STAGED, 1>(r, st, c, y, got);  // unread terms are 0.0f
 #pragma unroll
     for (int t = 0; t < U; ++t) acc += __uint_as_float(y[t]);
     return acc;
@@ -148,6 +152,7 @@ struct Real {
 // Boolean (|, &): x_k = A (x) f_{k-1}; f_k = x_k & g_k with a uint8 frontier.
 struct Boolean {
   static constexpr bool kSingleRoot = true;
+  static constexpr int kFilterShift = 2;  // filter up to a quarter of the chunks
   using Acc = uint32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -156,12 +161,12 @@ struct Boolean {
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED, class F>
+  template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc, F&& issued) {
+                              Acc acc) {
     uint32_t y[U];
     bool got[U];
-    gather_rows<U, STAGED, 0>(r, st, c, y, got, issued);  // unread terms are 0
+    gather_rows<U, STAGED, 0>(r, st, c, y, got);  // unread terms are 0
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -202,6 +207,7 @@ struct Boolean {
 // evaluated exactly while the gathered array is 32 times smaller.
 struct SelMax {
   static constexpr bool kSingleRoot = true;
+  static constexpr int kFilterShift = 2;  // filter up to a quarter of the chunks
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -212,13 +218,13 @@ struct SelMax {
   }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED, class F>
+  template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc, F&& issued) {
+                              Acc acc) {
     const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
     uint32_t w[U];  // the 32-bit half of the chunk word holding bit c (0 if unread)
     bool got[U];
-    gather_rows<U, STAGED, 2>(r, st, c, w, got, issued);
+    gather_rows<U, STAGED, 2>(r, st, c, w, got);
     bool hit[U];
     bool some = false;
 #pragma unroll
@@ -273,6 +279,7 @@ struct SelMax {
 // slot its graph uses has reached it.
 struct Batch {
   static constexpr bool kSingleRoot = false;
+  static constexpr int kFilterShift = 0;  // never filtered (no summary)
   using Acc = unsigned long long;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = false;
@@ -284,13 +291,12 @@ struct Batch {
     return (a.vis[row] & full) != full;
   }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
-  template <int U, bool STAGED, class F>
+  template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc, F&& issued) {
+                              Acc acc) {
     Acc y[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, off_of(c[t], 3));
-    issued();
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -353,18 +359,16 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
     p += (int64_t)U * kC;
     if (VAL) pv += (int64_t)U * kC;
     for (j = U; j + U <= ncols; j += U) {
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        nc[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
+        if (VAL) nw[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
+      }
       if (VAL) {
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      // the next block's loads are issued right behind this block's gathers
-      acc = S::template block<U, STAGED>(a, r, st, c, acc, [&] {
-#pragma unroll
-        for (int t = 0; t < U; ++t) {
-          nc[t] = __builtin_nontemporal_load(p + (int64_t)t * kC);
-          if (VAL) nw[t] = __builtin_nontemporal_load(pv + (int64_t)t * kC);
-        }
-      });
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
         go = false;
         break;
@@ -382,7 +386,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
       go = !(S::kFirstHitFinal && stop && S::settled(acc));
       cols = j;
     } else {
@@ -402,7 +406,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
         pv += (int64_t)U * kC;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
+      acc = S::template block<U, STAGED>(a, r, st, c, acc);
       p += (int64_t)U * kC;
       cols = j + U;
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
@@ -425,7 +429,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
     }
 #pragma unroll
     for (int t = 0; t < U; ++t) c[t] = t < rem ? c[t] : -1;
-    acc = S::template block<U, STAGED>(a, r, st, c, acc, [] {});
+    acc = S::template block<U, STAGED>(a, r, st, c, acc);
     cols = ncols;
   }
   return acc;
@@ -531,20 +535,33 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   }
   if (STAGED) {
     // copy the vector's first a.lds_bytes (a multiple of 16) into LDS, then
-    // the previous level's frontier summary behind it
+    // the previous level's frontier summary behind it, counting its set bits
+    __shared__ uint32_t flagged;
+    if (a.summ) {
+      if (threadIdx.x == 0) flagged = 0u;
+      __syncthreads();
+    }
     const uint4* src = static_cast<const uint4*>(S::staged(a));
     uint4* dst = reinterpret_cast<uint4*>(lds_stage);
     for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
-    uint32_t* sd = reinterpret_cast<uint32_t*>(lds_stage + a.lds_bytes);
     if (a.summ) {
       const uint32_t* prev = a.summ + (int64_t)((a.level - 1) % 3) * a.summ_words;
-      for (int32_t i = threadIdx.x; i < a.summ_words; i += blockDim.x) sd[i] = prev[i];
-      st.summ_mask = ~0u;
-    } else if (threadIdx.x == 0) {
-      sd[0] = ~0u;  // no summary: every chunk counts as holding frontier rows
+      uint32_t* sd = reinterpret_cast<uint32_t*>(lds_stage + a.lds_bytes);
+      uint32_t cnt = 0u;
+      for (int32_t i = threadIdx.x; i < a.summ_words; i += blockDim.x) {
+        const uint32_t w = prev[i];
+        sd[i] = w;
+        cnt += (uint32_t)__popc(w);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+      if (lane == 0 && cnt) atomicAdd(&flagged, cnt);
     }
     __syncthreads();
     st.bytes = a.lds_bytes;
+    // the filter pays when few chunks hold frontier rows (the same decision
+    // in every workgroup: all count the same summary)
+    if (a.summ) st.filter = ((uint64_t)flagged << S::kFilterShift) <= (uint64_t)(a.n_pad / kC);
   }
   // per-wavefront tallies, flushed once at the end
   uint32_t found = 0, n_chunks = 0;
