@@ -271,15 +271,15 @@ typedef struct {
  * instead of 4.  Built on the device at first use (2 x 4 B per cell).  Same
  * results; single-root levels only (no schedule, no persistent launch). */
 #define SS_SELL_VAL 8
-/* Plain single-root runs under tropical, real and boolean record, per level,
- * one bit per chunk that gained frontier rows (a frontier summary, 2 KiB per
- * million vertices, kept where it is at most 32 KiB).  While few chunks hold
- * frontier rows, the next level stages it in LDS and reads a term of the
- * product from memory only when its row's chunk holds frontier rows; every
- * other term is the semiring's identity for each row whose value can still
- * change, so results are unchanged.  This flag turns the summary off (every
- * term outside the staged prefix is read).  Sel-max runs, runs with a
- * schedule and the batched SpMM never use it. */
+/* Plain single-root runs record, per level, one bit per chunk that gained
+ * frontier rows (a frontier summary, 2 KiB per million vertices, kept where it
+ * is at most 32 KiB).  While few chunks hold frontier rows, the next level
+ * stages it in LDS and reads a term of the product from memory only when its
+ * row's chunk holds frontier rows; every other term is the semiring's
+ * identity for each row whose value can still change, so results are
+ * unchanged.  A level records its summary only if it used one itself.  This
+ * flag turns the summary off (every term outside the staged prefix is read).
+ * Runs with a schedule and the batched SpMM never use it. */
 #define SS_NO_SUMMARY 32
 
 /*

@@ -220,7 +220,8 @@ static int alloc_workspace(Graph& g) {
   // enough to sit in LDS beside the staged prefix
   const int64_t summ_words = (g.n_chunks + 31) / 32;
   if (summ_words * 4 <= kSummMaxBytes) {
-    if ((rc = dalloc(&ws.summ, 3 * summ_words))) return rc;
+    // three summaries, then one word per summary: whether its level wrote it
+    if ((rc = dalloc(&ws.summ, 3 * summ_words + 4))) return rc;
     ws.summ_words = (int32_t)summ_words;
   }
   void* h = nullptr;
@@ -345,13 +346,11 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   }
   if (o->schedule < 0 || o->schedule > 3 + kVariants - 1)
     return set_error(SS_EINVAL, "schedule must be 0..6");
-  // Plain single-root runs under tropical, real and boolean keep one summary
-  // bit per chunk of each level's frontier and skip the gathers of chunks
-  // without frontier rows.  Sel-max does not: its gathered bitmap is one bit
-  // per row, so the LDS prefix already serves most terms and the summary's
-  // upkeep costs more than it saves.  Push levels of a scheduled run do not
-  // maintain it, and the batched masks are not filtered.
-  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring && policy != SS_SELMAX &&
+  // Plain single-root runs keep one summary bit per chunk of each level's
+  // frontier and skip the gathers of chunks without frontier rows.  Push
+  // levels of a scheduled run do not maintain it, and the batched masks are
+  // not filtered.
+  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring &&
             !(o->flags & SS_NO_SUMMARY) &&
             (int64_t)p->lds_bytes + 4 * (int64_t)g.ws.summ_words <= g.lds_dev;
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");

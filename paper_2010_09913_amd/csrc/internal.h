@@ -93,7 +93,8 @@ struct Workspace {
   int32_t* pstatus = nullptr;           // [4] persistent run: levels, error, level cap
   // frontier summaries: one bit per chunk, set when a row of the chunk entered
   // the frontier; three buffers of summ_words words (level k writes k mod 3,
-  // reads k - 1 mod 3 and clears k + 1 mod 3); nullptr when too large
+  // reads k - 1 mod 3 and clears k + 1 mod 3), then three words saying
+  // whether the level wrote its buffer; nullptr when too large
   uint32_t* summ = nullptr;
   int32_t summ_words = 0;
   // host-mapped report ring written by the GPU: (tag << 1) | found

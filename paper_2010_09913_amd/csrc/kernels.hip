@@ -48,9 +48,8 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
   static constexpr bool kSingleRoot = true;
-  // frontier-summary filter at every density: with 4 bytes per row, terms
-  // outside the LDS prefix are most terms, and skipping some always pays
-  static constexpr int kFilterShift = 0;
+  // frontier-summary filter while at most half of the chunks hold frontier rows
+  static constexpr int kFilterShift = 1;
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -103,7 +102,7 @@ struct Tropical {
 // exact in fp32.
 struct Real {
   static constexpr bool kSingleRoot = true;
-  static constexpr int kFilterShift = 0;  // filter at every density (as tropical)
+  static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = float;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = false;
@@ -443,11 +442,11 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane
 template <class S>
 __device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chunk, int32_t row,
                                                 typename S::Acc acc, bool live, int lane,
-                                                uint64_t& fdeg) {
+                                                bool record, uint64_t& fdeg) {
   const bool fresh = S::post(a, row, acc, live);
   const uint64_t mask = __ballot(fresh);
   S::publish(a, chunk, mask, lane);
-  if (a.summ && lane == 0 && mask)  // the chunk has a frontier row for the next level
+  if (record && lane == 0 && mask)  // the chunk has a frontier row for the next level
     atomicOr(a.summ + (int64_t)(a.level % 3) * a.summ_words + (chunk >> 5), 1u << (chunk & 31));
   if (fresh) fdeg += (uint64_t)a.deg[row];
   return (uint32_t)__popcll(mask);
@@ -533,18 +532,20 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
          i += (int64_t)gridDim.x * blockDim.x)
       next[i] = 0u;
   }
+  // the previous level left a summary only if it used one itself
+  const bool have = a.summ && a.summ[3 * (int64_t)a.summ_words + (a.level - 1) % 3] != 0u;
   if (STAGED) {
     // copy the vector's first a.lds_bytes (a multiple of 16) into LDS, then
     // the previous level's frontier summary behind it, counting its set bits
     __shared__ uint32_t flagged;
-    if (a.summ) {
+    if (have) {
       if (threadIdx.x == 0) flagged = 0u;
       __syncthreads();
     }
     const uint4* src = static_cast<const uint4*>(S::staged(a));
     uint4* dst = reinterpret_cast<uint4*>(lds_stage);
     for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
-    if (a.summ) {
+    if (have) {
       const uint32_t* prev = a.summ + (int64_t)((a.level - 1) % 3) * a.summ_words;
       uint32_t* sd = reinterpret_cast<uint32_t*>(lds_stage + a.lds_bytes);
       uint32_t cnt = 0u;
@@ -561,8 +562,14 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
     st.bytes = a.lds_bytes;
     // the filter pays when few chunks hold frontier rows (the same decision
     // in every workgroup: all count the same summary)
-    if (a.summ) st.filter = ((uint64_t)flagged << S::kFilterShift) <= (uint64_t)(a.n_pad / kC);
+    if (have) st.filter = ((uint64_t)flagged << S::kFilterShift) <= (uint64_t)(a.n_pad / kC);
   }
+  // A level records its own frontier summary only when it used the filter:
+  // after a level with a wide frontier the next one is usually wide too, and
+  // recording it would cost one atomic per chunk for nothing.
+  const bool record = STAGED && st.filter;
+  if (a.summ && blockIdx.x == 0 && threadIdx.x == 0)
+    a.summ[3 * (int64_t)a.summ_words + a.level % 3] = record ? 1u : 0u;
   // per-wavefront tallies, flushed once at the end
   uint32_t found = 0, n_chunks = 0;
   uint64_t n_cols = 0, fdeg = 0;
@@ -605,7 +612,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       n_cols += (uint64_t)wave_max(lane_cols);  // columns the wavefront streamed
       const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
-        found += finish_rows<S>(a, c, row, acc, live, lane, fdeg);
+        found += finish_rows<S>(a, c, row, acc, live, lane, record, fdeg);
       } else {
         // SlimChunk: combine this piece, the last one to arrive post-processes.
         // Pieces exchange data only through device-scope atomics: each piece's
@@ -619,7 +626,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
         if (last) {
           acc = S::take(a, row);
           if (lane == 0) a.arrive[c] = 0;
-          found += finish_rows<S>(a, c, row, acc, live, lane, fdeg);
+          found += finish_rows<S>(a, c, row, acc, live, lane, record, fdeg);
         }
       }
     }
@@ -1167,6 +1174,7 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
     const int32_t rc = root_row / kC;
     summ[r] = (r == rc >> 5) ? (1u << (rc & 31)) : 0u;
     summ[summ_words + r] = 0u;
+    if (r == 0) summ[3 * (int64_t)summ_words] = 1u;  // level 0's summary is valid
   }
   if (r >= n_pad) return;
   // sel-max: one bitmap word per chunk is initialised below
