@@ -71,3 +71,24 @@ def test_functions_read_only_bound_names(path):
         else:
             stack.extend(ast.iter_child_nodes(node))
     assert not problems, problems
+
+
+def test_header_constants_match_the_binding():
+    # every status code and flag the header defines has the same value in the
+    # ctypes binding (a drifted flag would silently select another mode)
+    import re
+    from paper_2010_09913_amd import _native
+    hdr = open(os.path.join(ROOT, "include", "slimsell.h")).read()
+    consts = {m.group(1): int(m.group(2))
+              for m in re.finditer(r"^#define\s+(SS_[A-Z_]+)\s+(-?\d+)", hdr, re.M)}
+    consts.update({m.group(1): int(m.group(2))
+                   for m in re.finditer(r"^\s+(SS_E[A-Z]+|SS_OK)\s*=\s*(-?\d+)", hdr, re.M)})
+    flags = {k: v for k, v in consts.items()
+             if k.startswith(("SS_STATS_", "SS_RUN_", "SS_SELL_", "SS_NO_")) or k.startswith("SS_E")
+             or k == "SS_OK"}
+    assert {"SS_NO_SUMMARY", "SS_SELL_VAL", "SS_EITER", "SS_OK"} <= set(flags)
+    for name, value in flags.items():
+        assert getattr(_native, name) == value, name
+    # flags are distinct single bits
+    bits = [v for k, v in flags.items() if not (k.startswith("SS_E") or k == "SS_OK")]
+    assert len(set(bits)) == len(bits) and all(b > 0 and b & (b - 1) == 0 for b in bits)
