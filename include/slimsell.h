@@ -277,9 +277,10 @@ typedef struct {
  * stages it in LDS and reads a term of the product from memory only when its
  * row's chunk holds frontier rows; every other term is the semiring's
  * identity for each row whose value can still change, so results are
- * unchanged.  A level records its summary only if it used one itself.  This
- * flag turns the summary off (every term outside the staged prefix is read).
- * Runs with a schedule and the batched SpMM never use it. */
+ * unchanged.  A level records its summary only if it used one itself.  The
+ * batched SpMM keeps one too (a chunk is flagged when a row gained root
+ * bits).  This flag turns the summary off (every term outside the staged
+ * prefix is read).  Runs with a schedule never use it. */
 #define SS_NO_SUMMARY 32
 
 /*

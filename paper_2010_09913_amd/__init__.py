@@ -304,7 +304,7 @@ class Graph:
 
     def bfs_batch(self, roots, *, slimwork: int = 2, max_levels: int = 0, stream=None,
                   level_cap: int = 0, timing: bool = False, counters: bool = None,
-                  persistent: bool = False, dist=None):
+                  persistent: bool = False, summary: bool = True, dist=None):
         """Batched BFS (64-bit frontier masks).  roots: int array [num_graphs, rpg]
         (graph-local IDs, -1 = unused slot) or [rpg] for a single graph.  Returns
         (dist tensor, iterations, levels, runs); dist holds each graph's block
@@ -329,7 +329,8 @@ class Graph:
             counters = level_cap > 0
         o.flags = (_native.SS_STATS_TIME if timing else 0) | (
             _native.SS_STATS_COUNTERS if counters else 0) | (
-            _native.SS_RUN_PERSISTENT if persistent else 0)
+            _native.SS_RUN_PERSISTENT if persistent else 0) | (
+            0 if summary else _native.SS_NO_SUMMARY)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * level_cap)()

@@ -346,11 +346,10 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   }
   if (o->schedule < 0 || o->schedule > 3 + kVariants - 1)
     return set_error(SS_EINVAL, "schedule must be 0..6");
-  // Plain single-root runs keep one summary bit per chunk of each level's
-  // frontier and skip the gathers of chunks without frontier rows.  Push
-  // levels of a scheduled run do not maintain it, and the batched masks are
-  // not filtered.
-  p->summ = g.ws.summ && !o->schedule && policy != kBatchSemiring &&
+  // Plain runs (single-root and batched) keep one summary bit per chunk of
+  // each level's frontier and skip the gathers of chunks without frontier
+  // rows.  Push levels of a scheduled run do not maintain it.
+  p->summ = g.ws.summ && !o->schedule &&
             !(o->flags & SS_NO_SUMMARY) &&
             (int64_t)p->lds_bytes + 4 * (int64_t)g.ws.summ_words <= g.lds_dev;
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
@@ -1006,7 +1005,7 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
   RunLog log(1);
   const uint32_t run = next_run_id(g);
   if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[0]))) return rc;
-  rc = launch_batch_init(g, bw, (int32_t)root_rows.size(), st);
+  rc = launch_batch_init(g, bw, (int32_t)root_rows.size(), plan.summ, st);
   if (rc) return rc;
   LevelArgs a = base_args(g, plan, o, run, 0);
   a.acc64 = bw.acc64;

@@ -143,6 +143,47 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
   }
 }
 
+// The same for the batched SpMM's 64-bit masks (8 bytes per row): with the
+// filter on, a mask outside the prefix is read only when its row's chunk
+// gained frontier bits in the previous level; unread masks are 0.
+template <int U, bool STAGED>
+__device__ __forceinline__ void gather_masks(Rsrc r, Stage st, const int32_t (&c)[U],
+                                             unsigned long long (&y)[U]) {
+  if (!STAGED || !st.filter) {
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, c[t] >= 0 ? (uint32_t)c[t] << 3 : kOob);
+    return;
+  }
+  uint32_t o[U];
+  bool some = false;
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const bool valid = c[t] >= 0;
+    const uint32_t cu = valid ? (uint32_t)c[t] : 0u;
+    const uint32_t off = valid ? cu << 3 : kOob;
+    const bool in = off < st.bytes;
+    // the staged mask, or (as its low word) the summary word of the chunk
+    const uint32_t sw = st.bytes + ((cu >> 11) << 2);
+    unsigned long long v;
+    if (in) {
+      v = *reinterpret_cast<const unsigned long long*>(st.lds + off);
+    } else {
+      v = *reinterpret_cast<const uint32_t*>(st.lds + sw);
+    }
+    y[t] = in ? v : 0ull;
+    const uint32_t need = (valid && !in ? 1u : 0u) & ((uint32_t)v >> ((cu >> 6) & 31u));
+    o[t] = need ? off : kOob;
+    some = some || need;
+  }
+  if (__any(some)) {
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, o[t], 0, 0);
+      y[t] |= ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
+    }
+  }
+}
+
 __device__ __forceinline__ int32_t wave_max(int32_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {

@@ -286,7 +286,8 @@ int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream);
 // Sell-C-sigma arrays from the SlimSell col (same shape).
 int launch_sell_build(const int32_t* col, int64_t cells, int32_t* scol, int32_t* sval,
                       void* stream);
-int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, void* stream);
+int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, bool summary,
+                      void* stream);
 int launch_batch_finalise(const Graph& g, const BatchWorkspace& b, int32_t rpg, int32_t* dist,
                           void* stream);
 int launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t count, void* stream);

@@ -278,7 +278,7 @@ struct SelMax {
 // slot its graph uses has reached it.
 struct Batch {
   static constexpr bool kSingleRoot = false;
-  static constexpr int kFilterShift = 0;  // never filtered (no summary)
+  static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = unsigned long long;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = false;
@@ -294,8 +294,7 @@ struct Batch {
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
                               Acc acc) {
     Acc y[U];
-#pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, off_of(c[t], 3));
+    gather_masks<U, STAGED>(r, st, c, y);  // unread masks are 0
 #pragma unroll
     for (int t = 0; t < U; ++t) acc |= y[t];
     return acc;
@@ -1238,9 +1237,16 @@ __global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* s
 // final); then each used root slot sets its bit and level 0 at its root row.
 __global__ void batch_init_kernel(int32_t n_pad, int64_t n_chunks, const int32_t* v,
                                   unsigned long long* vis, unsigned long long* fa,
-                                  unsigned long long* acc64, int32_t* arrive) {
+                                  unsigned long long* acc64, int32_t* arrive, uint32_t* summ,
+                                  int32_t summ_words) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_chunks) arrive[r] = 0;
+  if (summ && r < summ_words) {
+    // level 0's summary gets the roots' chunks (next kernel); level 1's starts empty
+    summ[r] = 0u;
+    summ[summ_words + r] = 0u;
+    if (r == 0) summ[3 * (int64_t)summ_words] = 1u;  // level 0's summary is valid
+  }
   if (r >= n_pad) return;
   vis[r] = (v[r] == 0) ? ~0ull : 0ull;
   fa[r] = 0ull;
@@ -1249,13 +1255,14 @@ __global__ void batch_init_kernel(int32_t n_pad, int64_t n_chunks, const int32_t
 
 __global__ void batch_roots_kernel(int32_t count, const int32_t* root_rows, const int32_t* slots,
                                    unsigned long long* vis, unsigned long long* fa,
-                                   uint16_t* lvl) {
+                                   uint16_t* lvl, uint32_t* summ) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int32_t row = root_rows[i];
   const unsigned long long bit = 1ull << slots[i];
   atomicOr(&vis[row], bit);
   atomicOr(&fa[row], bit);
+  if (summ) atomicOr(&summ[row / kC >> 5], 1u << ((row / kC) & 31));
   lvl[(int64_t)row * 64 + slots[i]] = 0;
 }
 
@@ -1273,9 +1280,21 @@ __global__ void batch_finalise_kernel(int64_t n, int32_t num_graphs, const int64
   const int64_t base = voff[lo], ni = voff[lo + 1] - base;
   const int32_t row = perm[o];
   const unsigned long long seen = vis[row];
-  const uint16_t* lv = lvl + (int64_t)row * 64;
+  // the row's level record is 128 contiguous bytes: read it 16 bytes (eight
+  // slots) at a time instead of one 2-byte load per slot
+  const uint4* lv = reinterpret_cast<const uint4*>(lvl + (int64_t)row * 64);
   int32_t* out = dist + (int64_t)rpg * base + (o - base);
-  for (int32_t b = 0; b < rpg; ++b) out[(int64_t)b * ni] = ((seen >> b) & 1ull) ? (int32_t)lv[b] : -1;
+  for (int32_t q = 0; q * 8 < rpg; ++q) {
+    const uint4 w = lv[q];
+    const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t b = q * 8 + k;
+      if (b >= rpg) break;
+      const int32_t level = (int32_t)((x[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu);
+      out[(int64_t)b * ni] = ((seen >> b) & 1ull) ? level : -1;
+    }
+  }
 }
 
 template <class T>
@@ -1538,14 +1557,17 @@ int launch_fill_i32(int32_t* p, int32_t value, int64_t count, void* stream) {
   return check_launch("fill_kernel");
 }
 
-int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, void* stream) {
+int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, bool summary,
+                      void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* summ = summary ? g.ws.summ : nullptr;
   batch_init_kernel<<<blocks_for(g.n_pad, 256), 256, 0, st>>>(g.n_pad, g.n_chunks, g.d_v, b.vis,
-                                                              b.fa, b.acc64, g.ws.arrive);
+                                                              b.fa, b.acc64, g.ws.arrive, summ,
+                                                              g.ws.summ_words);
   int rc = check_launch("batch_init_kernel");
   if (rc || count == 0) return rc;
   batch_roots_kernel<<<blocks_for(count, 256), 256, 0, st>>>(count, b.root_rows, b.slots, b.vis,
-                                                             b.fa, b.lvl);
+                                                             b.fa, b.lvl, summ);
   return check_launch("batch_roots_kernel");
 }
 
