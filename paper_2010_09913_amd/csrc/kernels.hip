@@ -1284,15 +1284,21 @@ __global__ void batch_finalise_kernel(int64_t n, int32_t num_graphs, const int64
   // slots) at a time instead of one 2-byte load per slot
   const uint4* lv = reinterpret_cast<const uint4*>(lvl + (int64_t)row * 64);
   int32_t* out = dist + (int64_t)rpg * base + (o - base);
-  for (int32_t q = 0; q * 8 < rpg; ++q) {
-    const uint4 w = lv[q];
-    const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+  const int32_t nq = (rpg + 7) / 8;
+  uint4 w[8];  // all loads in flight before the first store
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w[q] = q < nq ? lv[q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int32_t b = q * 8 + k;
-      if (b >= rpg) break;
-      const int32_t level = (int32_t)((x[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu);
-      out[(int64_t)b * ni] = ((seen >> b) & 1ull) ? level : -1;
+      if (b < rpg) {
+        const int32_t level = (int32_t)((x[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu);
+        // every output is written once and never read here: stream it
+        __builtin_nontemporal_store(((seen >> b) & 1ull) ? level : -1, out + (int64_t)b * ni);
+      }
     }
   }
 }
