@@ -1219,18 +1219,18 @@ __global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* s
                                 float* real_val) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
-  const int32_t row = perm[o];
+  // the outputs are written once and not read again here: streaming stores
+  const int32_t row = __builtin_nontemporal_load(perm + o);
   if (SEMI == SS_TROPICAL) {
     const int32_t f = state[row];
-    dist[o] = (f >= kInf) ? -1 : f;
+    __builtin_nontemporal_store((f >= kInf) ? -1 : f, dist + o);
     return;
   }
-  dist[o] = d[row];
-  if (SEMI == SS_SELMAX && parent) {
-    const int32_t pr = state[row];
-    parent[o] = (pr > 0) ? pr - 1 : -1;
-  }
-  if (SEMI == SS_REAL && real_val) real_val[o] = rv[row];
+  const int32_t dr = d[row];
+  const int32_t pr = (SEMI == SS_SELMAX && parent) ? state[row] : 0;
+  __builtin_nontemporal_store(dr, dist + o);
+  if (SEMI == SS_SELMAX && parent) __builtin_nontemporal_store((pr > 0) ? pr - 1 : -1, parent + o);
+  if (SEMI == SS_REAL && real_val) __builtin_nontemporal_store(rv[row], real_val + o);
 }
 
 // Batched level 0: every row starts with an empty mask (phantom rows are
