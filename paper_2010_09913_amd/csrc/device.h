@@ -18,9 +18,6 @@ constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
 __device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
-__device__ __forceinline__ uint32_t off_of(int32_t c, int shift) {
-  return c >= 0 ? ((uint32_t)c << shift) : kOob;
-}
 
 // Returning atomics are passed through keep(), so that wait_memory() (all of
 // this wavefront's vector memory operations done) covers their completion.
@@ -82,8 +79,8 @@ __device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint3
 // product is then the semiring's identity.  The filter costs an LDS round
 // trip before the memory gathers, so levels whose frontier touches many
 // chunks run without it.
-template <int U, bool STAGED, int KIND>
-__device__ __forceinline__ uint32_t row_offset(int32_t c) {
+template <int KIND>
+__device__ __forceinline__ uint32_t row_offset(int32_t c) {  // byte offset of row c's element
   const uint32_t cu = (uint32_t)c;
   return c < 0 ? kOob : KIND == 0 ? cu : KIND == 1 ? (cu << 2) : ((cu >> 5) << 2);
 }
@@ -96,7 +93,7 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     // masked, the buffer load gets an out-of-range offset when LDS serves it)
 #pragma unroll
     for (int t = 0; t < U; ++t) {
-      const uint32_t off = row_offset<U, STAGED, KIND>(c[t]);
+      const uint32_t off = row_offset<KIND>(c[t]);
       const bool in = STAGED && off < st.bytes;
       uint32_t l = 0u;
       if (STAGED) {
@@ -116,7 +113,7 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
   for (int t = 0; t < U; ++t) {
     const bool valid = c[t] >= 0;
     const uint32_t cu = valid ? (uint32_t)c[t] : 0u;
-    const uint32_t off = row_offset<U, STAGED, KIND>(c[t]);
+    const uint32_t off = row_offset<KIND>(c[t]);
     const bool in = off < st.bytes;
     // one LDS read per term: the staged element if the prefix holds it,
     // else the summary word of its chunk (stored right behind the prefix)
@@ -139,7 +136,7 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     y[t] |= g[t];
-    got[t] = o[t] != kOob || row_offset<U, STAGED, KIND>(c[t]) < st.bytes;
+    got[t] = o[t] != kOob || row_offset<KIND>(c[t]) < st.bytes;
   }
 }
 

@@ -104,7 +104,7 @@ struct Real {
   static constexpr bool kSingleRoot = true;
   static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = float;
-  // the first product term a row receives is its final value
+  // a row's value is known only after all its terms (a sum of frontier terms)
   static constexpr bool kFirstHitFinal = false;
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0.0f; }
@@ -280,7 +280,7 @@ struct Batch {
   static constexpr bool kSingleRoot = false;
   static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = unsigned long long;
-  // the first product term a row receives is its final value
+  // a row's masks are known only after all its terms (an OR over neighbours)
   static constexpr bool kFirstHitFinal = false;
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0ull; }
@@ -347,7 +347,8 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
   if (ncols >= 2 * U) {
     // Software pipeline: the next block's col (and val) loads are in flight
     // while this block's gathers (which depend on its col values) are
-    // served, so a block costs one memory latency instead of two.
+    // served, so a block costs one memory latency instead of two.  (A second
+    // block of depth measured no faster and costs U more registers.)
     int32_t c[U], w[U], nc[U], nw[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
