@@ -92,3 +92,38 @@ def test_filter_in_the_persistent_form_and_repeated_runs(ss):
         torch.cuda.synchronize()
         _compare(res, exs[::-1], semi)
     G.close()
+
+
+def test_batched_masks_with_and_without_the_summary(ss):
+    # the batched SpMM keeps a summary of chunks whose rows gained root bits;
+    # distances with it on and off must both be the oracle's, on one graph
+    # and on a union of uneven graphs (persistent form included)
+    import torch
+    graphs = [graphgen.er(int(n), int(4 * n), seed=90 + i) for i, n in enumerate([70, 1, 3000])]
+    graphs.append(graphgen.grid(40, 30, 0.05, seed=93))
+    graphs.append(graphgen.rmat(12, 16, seed=94))
+    csrs = [oracle.csr_from_edgelist(g) for g in graphs]
+    G = ss.Graph.from_many(graphs)
+    ns, off = G.parts()
+    rpg = 64
+    roots = np.full((len(graphs), rpg), -1, np.int32)
+    for i, g in enumerate(graphs):
+        rr = graphgen.pick_roots(g, rpg, seed=300 + i)
+        roots[i, :len(rr)] = rr
+        if len(rr) == 0:
+            roots[i, 0] = 0
+    for summary in (True, False):
+        for persistent in (False, True):
+            note("batched summary", summary, "persistent", persistent)
+            dist, _, _, _ = G.bfs_batch(roots, summary=summary, persistent=persistent)
+            torch.cuda.synchronize()
+            d = dist.cpu().numpy()
+            for i, c in enumerate(csrs):
+                blk = d[rpg * off[i]: rpg * (off[i] + ns[i])].reshape(rpg, ns[i])
+                for b in (0, 1, 31, 63):
+                    r = int(roots[i, b])
+                    if r < 0:
+                        assert np.all(blk[b] == -1)
+                    else:
+                        np.testing.assert_array_equal(blk[b], oracle.bfs(c, r))
+    G.close()
