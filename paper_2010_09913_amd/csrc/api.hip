@@ -284,7 +284,8 @@ struct RunPlan {
   int64_t max_groups = 0, cap = 0, lcap = 0, words_per_run = 0;
   bool timing = false, counting = false, persistent = false, sell = false;
   bool level_events = false;  // timing: events around every level launch too
-  bool summ = false;          // frontier summaries filter the gathers (plain single-root runs)
+  bool summ = false;          // frontier summaries filter the gathers (plain runs)
+  int32_t filter_limit = 0;   // most flagged chunks for which a level filters
   int32_t slimwork = 2;
   int32_t schedule = 0;
   uint32_t lds_bytes = 0;
@@ -352,6 +353,29 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   p->summ = g.ws.summ && !o->schedule &&
             !(o->flags & SS_NO_SUMMARY) &&
             (int64_t)p->lds_bytes + 4 * (int64_t)g.ws.summ_words <= g.lds_dev;
+  if (p->summ) {
+    // The filter skips the memory gathers of unflagged chunks but puts an
+    // LDS round trip before the others, so it pays while the terms it can
+    // skip are many: (share of terms outside the LDS prefix) x (share of
+    // unflagged chunks) at least kFilterTau.  The first share follows from
+    // the row degrees (a symmetric matrix: row r is the column of deg(r)
+    // cells) and the rows the prefix holds for this semiring's element size.
+    constexpr double kFilterTau = 1.0 / 16;
+    const int64_t rows = policy == SS_SELMAX    ? (int64_t)p->lds_bytes * 8
+                         : policy == SS_BOOLEAN ? (int64_t)p->lds_bytes
+                         : policy == kBatchSemiring ? (int64_t)p->lds_bytes / 8
+                                                    : (int64_t)p->lds_bytes / 4;
+    const int64_t nc = g.n_chunks;
+    const int64_t in_chunks = std::min<int64_t>(rows / kC, nc);
+    const double total = nc > 0 ? (double)g.h_chunk_deg[(size_t)nc] : 0.0;
+    const double outside = total > 0 ? 1.0 - (double)g.h_chunk_deg[(size_t)in_chunks] / total : 0.0;
+    const double frac = outside > kFilterTau ? 1.0 - kFilterTau / outside : 0.0;
+    // the share of unflagged chunks counts chunks that have rows with
+    // neighbours (a chunk of isolated rows is never flagged)
+    int64_t nonempty = 0;
+    for (int32_t len : g.h_cl) nonempty += len > 0 ? 1 : 0;
+    p->filter_limit = (int32_t)std::floor(frac * (double)nonempty);
+  }
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
   p->schedule = o->schedule;
   int rc = get_units(g, split, pack, &p->ul);
@@ -425,6 +449,7 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
   a.lds_bytes = p.lds_bytes;
   a.summ = p.summ ? g.ws.summ : nullptr;
   a.summ_words = g.ws.summ_words;
+  a.filter_limit = p.filter_limit;
   if (p.schedule) {
     a.variant = g.ws.variant;
     for (int v = 0; v < kPullVariants; ++v) {
@@ -801,6 +826,13 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
   g->h_roff = {0, (int64_t)L->n_pad};
   g->h_degree.resize((size_t)L->n);
   for (int32_t o = 0; o < L->n; ++o) g->h_degree[o] = L->degree[L->perm[o]];
+  g->h_chunk_deg.assign((size_t)L->n_chunks + 1, 0);
+  for (int64_t c = 0; c < L->n_chunks; ++c) {
+    int64_t sum = 0;
+    for (int64_t r = c * kC; r < (c + 1) * kC && r < (int64_t)L->degree.size(); ++r)
+      sum += L->degree[(size_t)r];
+    g->h_chunk_deg[(size_t)c + 1] = g->h_chunk_deg[(size_t)c] + sum;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = SS_OK;
   auto up = [&](auto** dst, const auto& vec) -> int {

@@ -153,6 +153,10 @@ struct Graph {
   std::vector<int32_t> h_perm;  // row of each original vertex
   std::vector<int32_t> h_cl;    // chunk lengths (for unit decomposition)
   std::vector<int32_t> h_degree;  // degree of each original vertex
+  // prefix sums over chunks of the row degrees: the cells whose column lies
+  // in the first k chunks of rows number h_chunk_deg[k] (the matrix is
+  // symmetric), which says how many gathers an LDS prefix of rows serves
+  std::vector<int64_t> h_chunk_deg;
   std::vector<void*> ev_pool;     // hipEvent_t pool for SS_STATS_TIME
   std::map<std::pair<int32_t, int32_t>, UnitList> units;  // by (split_len, pack_cols)
   Workspace ws;
@@ -213,6 +217,7 @@ struct LevelArgs {
   uint32_t lds_bytes;  // prefix of the gathered vector staged in LDS (0 = none)
   uint32_t* summ;      // frontier summaries (Workspace::summ) or nullptr: no gather filter
   int32_t summ_words;
+  int32_t filter_limit;  // filter while at most this many chunks hold frontier rows
   int32_t level;     // k >= 1
   int32_t slimwork;
   int32_t count_stats;

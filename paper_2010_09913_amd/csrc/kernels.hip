@@ -48,8 +48,6 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
   static constexpr bool kSingleRoot = true;
-  // frontier-summary filter while at most half of the chunks hold frontier rows
-  static constexpr int kFilterShift = 1;
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -102,7 +100,6 @@ struct Tropical {
 // exact in fp32.
 struct Real {
   static constexpr bool kSingleRoot = true;
-  static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = float;
   // a row's value is known only after all its terms (a sum of frontier terms)
   static constexpr bool kFirstHitFinal = false;
@@ -151,7 +148,6 @@ struct Real {
 // Boolean (|, &): x_k = A (x) f_{k-1}; f_k = x_k & g_k with a uint8 frontier.
 struct Boolean {
   static constexpr bool kSingleRoot = true;
-  static constexpr int kFilterShift = 2;  // filter up to a quarter of the chunks
   using Acc = uint32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -206,7 +202,6 @@ struct Boolean {
 // evaluated exactly while the gathered array is 32 times smaller.
 struct SelMax {
   static constexpr bool kSingleRoot = true;
-  static constexpr int kFilterShift = 2;  // filter up to a quarter of the chunks
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -278,7 +273,6 @@ struct SelMax {
 // slot its graph uses has reached it.
 struct Batch {
   static constexpr bool kSingleRoot = false;
-  static constexpr int kFilterShift = 1;  // filter up to half of the chunks
   using Acc = unsigned long long;
   // a row's masks are known only after all its terms (an OR over neighbours)
   static constexpr bool kFirstHitFinal = false;
@@ -562,7 +556,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
     st.bytes = a.lds_bytes;
     // the filter pays when few chunks hold frontier rows (the same decision
     // in every workgroup: all count the same summary)
-    if (have) st.filter = ((uint64_t)flagged << S::kFilterShift) <= (uint64_t)(a.n_pad / kC);
+    if (have) st.filter = (int64_t)flagged <= (int64_t)a.filter_limit;
   }
   // A level records its own frontier summary only when it used the filter:
   // after a level with a wide frontier the next one is usually wide too, and
