@@ -273,9 +273,10 @@ typedef struct {
 #define SS_SELL_VAL 8
 /* Plain single-root runs record, per level, one bit per chunk that gained
  * frontier rows (a frontier summary, 2 KiB per million vertices, kept where it
- * is at most 32 KiB).  While few chunks hold frontier rows, the next level
- * stages it in LDS and reads a term of the product from memory only when its
- * row's chunk holds frontier rows; every other term is the semiring's
+ * is at most 32 KiB).  While few chunks hold frontier rows (how few depends
+ * on the share of gathers the LDS prefix serves), the next level stages it in
+ * LDS and reads a term of the product from memory only when its row's chunk
+ * holds frontier rows; every other term is the semiring's
  * identity for each row whose value can still change, so results are
  * unchanged.  A level records its summary only if it used one itself.  The
  * batched SpMM keeps one too (a chunk is flagged when a row gained root
