@@ -189,13 +189,15 @@ def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=Tru
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
+    r = None
     for _ in range(steps):
         r = G.bfs(roots, semi, split_len=split, timing="bfs", schedule=schedule,
                   persistent=persistent)
         runs.append(r.runs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out.update(wall=wall, runs=runs)
+    # the outputs of the last timed step, checked against the oracle later
+    out.update(wall=wall, runs=runs, result=r)
     # one more step, untimed, with events around every level launch (the
     # per-launch kernel time of the roofline)
     r = G.bfs(roots, semi, split_len=split, timing=True, schedule=schedule,
@@ -228,6 +230,17 @@ def summarise(out, roots, semi, n, nonempty_chunks, steps):
                  cells_per_bfs=float(np.mean([out["levels"]["active_cells"][i][:iters[i]].sum()
                                               for i in range(len(roots))])))
     return s
+
+
+def same_outputs(a, b) -> bool:
+    """Whether two BFS results of the same roots agree element by element
+    (distances, parents, iteration counts), compared on the device."""
+    import torch
+    ok = torch.equal(a.dist, b.dist) and np.array_equal(a.iterations, b.iterations)
+    if a.parent is not None or b.parent is not None:
+        ok = ok and a.parent is not None and b.parent is not None and \
+            torch.equal(a.parent, b.parent)
+    return bool(ok)
 
 
 def _events_ms(torch, fn, reps=3):
@@ -338,10 +351,11 @@ def bench_dp(G, roots, torch) -> dict:
     return out
 
 
-def bench_batched(ss, graphgen, torch) -> dict:
+def bench_batched(ss, graphgen, torch, checks: dict) -> dict:
     """64 roots in one boolean SpMM vs 64 plain runs (R-MAT s21), and 256
     Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], mean degree 8-64) in one
-    union solved by one level loop."""
+    union solved by one level loop.  Host copies of the outputs (all 64 slots
+    of s21, two slots of every ER graph) go to `checks` for the oracle."""
     e = graphgen.rmat(21, 16, seed=1)
     roots = graphgen.pick_roots(e, 64, seed=1004)
     G = ss.Graph.from_edgelist(e, sigma=0)
@@ -351,6 +365,7 @@ def bench_batched(ss, graphgen, torch) -> dict:
     dist, _, _, _ = G.bfs_batch(roots[None, :])
     d = dist.view(64, -1)
     m_cc = float(((d >= 0).to(torch.int64) * deg[None, :]).sum() // 2)
+    checks["batched_rmat_s21"] = [(e, roots, d.cpu().numpy())]
     G.bfs(roots, "selmax")
     t_plain = _events_ms(torch, lambda: G.bfs(roots, "selmax"), reps=2)
     G.bfs(roots, "boolean")
@@ -386,21 +401,25 @@ def bench_batched(ss, graphgen, torch) -> dict:
     degm = torch.from_numpy(Gm.degrees().astype(np.int64)).cuda()
     edges = 0.0
     dd = dist
+    sample = []
     for i in range(256):
         blk = dd[64 * off[i]: 64 * (off[i] + ns[i])].view(64, int(ns[i]))
         edges += float(((blk >= 0).to(torch.int64) * degm[off[i]:off[i] + ns[i]][None, :]).sum() // 2)
+        used = int((R[i] >= 0).sum())
+        slots = sorted({0, used - 1})
+        sample.append((graphs[i], R[i][slots], blk[slots].cpu().numpy()))
+    checks["batched_er_256"] = sample
     Gm.close()
     log(f"256 ER graphs: {t_many:.2f} ms (persistent {t_many_p:.2f}, autotuned {t_many_t:.2f} / "
         f"{t_many_tp:.2f}), {iters} levels, build {build:.1f}s")
-    best = min(t_many, t_many_p, t_many_t, t_many_tp)
+    forms = {"launch_per_level": t_many, "persistent": t_many_p,
+             "autotuned_launch_per_level": t_many_t, "autotuned_persistent": t_many_tp}
     out["er_256_graphs"] = {"vertices": int(ns.sum()), "roots": int((R >= 0).sum()),
-                            "levels": int(iters), "batched_ms": round(t_many, 3),
-                            "persistent_ms": round(t_many_p, 3),
-                            "autotuned_ms": round(t_many_t, 3),
-                            "autotuned_persistent_ms": round(t_many_tp, 3),
-                            "tune": at["best"], "tune_s": round(tune_s, 1),
-                            "gteps": round(edges / best / 1e6, 3),
-                            "build_s": round(build, 1)}
+                            "levels": int(iters), "tune": at["best"], "tune_s": round(tune_s, 1),
+                            "build_s": round(build, 1),
+                            "ms": {k: round(v, 3) for k, v in forms.items()},
+                            "gteps": {k: round(edges / v / 1e6, 3) for k, v in forms.items()},
+                            "fastest_form": min(forms, key=forms.get)}
     return out
 
 
@@ -421,13 +440,19 @@ def bench_learned(ss, graphgen, torch) -> dict:
         roots = graphgen.pick_roots(e, nroots, seed=seed)
         G = ss.Graph.from_edgelist(e, sigma=0)
         res = {}
+        first = None  # outputs of the first root under the first mode
+        agree = True
         for mode in ["learned", "heuristic", "pull", "pull-split256", "pull-split1024", "push",
                      "learned+persistent", "heuristic+persistent", "push+persistent"]:
             sched, pers = mode.split("+")[0], mode.endswith("+persistent")
             rr = roots
             if slow_roots and mode.startswith("pull"):
                 rr = roots[:slow_roots]   # pull-only on the grid is O(levels x n): few roots
-            G.bfs([int(rr[0])], "selmax", schedule=sched, persistent=pers)
+            x0 = G.bfs([int(rr[0])], "selmax", schedule=sched, persistent=pers)
+            if first is None:
+                first = x0
+            else:
+                agree = agree and same_outputs(first, x0)
             tot = 0.0
             for r in rr:
                 x = G.bfs([int(r)], "selmax", schedule=sched, timing="bfs", persistent=pers)
@@ -435,6 +460,7 @@ def bench_learned(ss, graphgen, torch) -> dict:
             res[mode] = round(tot / len(rr), 3)
             log(f"{name} {mode}: {tot / len(rr):.2f} ms per BFS")
         G.close()
+        res["forms_agree"] = bool(agree)
         res["learned_vs_heuristic"] = round(res["heuristic"] / res["learned"], 3)
         res["best_forced"] = min(("pull", "pull-split256", "pull-split1024", "push"),
                                  key=lambda m: res[m])
@@ -570,7 +596,8 @@ def main() -> int:
                 "_persistent" if pers else "")
             forms[name] = {"gteps": round(s2["gteps_wall"], 4),
                            "gteps_hmean": round(s2["gteps_hmean"], 4),
-                           "mean_bfs_ms": round(s2["mean_bfs_ms"], 4)}
+                           "mean_bfs_ms": round(s2["mean_bfs_ms"], 4),
+                           "same_outputs": same_outputs(out["result"], o2["result"])}
             log(f"{name}: {s2}")
         ss.sched_clear()
         default_tune = G.get_tune()
@@ -614,51 +641,112 @@ def main() -> int:
 
     if not args.only_timed and not args.no_extra:
         result["rmat_s20_sigma2^14"] = bench_scale20(ss, graphgen, torch)
+    checks = {"headline": [(e, roots, out["result"])]}
     if not args.only_timed and not args.no_batch:
-        result["batched"] = bench_batched(ss, graphgen, torch)
+        result["batched"] = bench_batched(ss, graphgen, torch, checks)
     if not args.only_timed and not args.no_learned:
         result["learned_schedule"] = bench_learned(ss, graphgen, torch)
 
     if not args.no_cpu and not args.only_timed:
-        import oracle
-        t = time.perf_counter()
-        g = oracle.csr_from_edgelist(e)
-        log(f"oracle CSR in {time.perf_counter() - t:.1f}s")
-        sample = roots[: args.cpu_roots]
-        rates = []
-        t_all = time.perf_counter()
-        for r in sample:
-            t = time.perf_counter()
-            d = oracle.bfs(g, int(r))
-            oracle.parents_max(g, int(r), d)
-            dt = time.perf_counter() - t
-            rates.append(oracle.component_edges(g, d) / dt)
-        cpu_s = time.perf_counter() - t_all
-        rates = np.array(rates)
-        result["cpu_baseline"] = {
-            "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
-            "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{len(sample)} of the {len(roots)} roots: FIFO-queue BFS + max-ID parent "
-                      f"pass (the sel-max outputs), 1 thread, {cpu_s:.1f}s total",
-        }
-        # the level-synchronous OpenMP oracle on all host threads (distances)
-        rates = []
-        t_all = time.perf_counter()
-        for r in sample:
-            t = time.perf_counter()
-            d = oracle.bfs_omp(g, int(r))
-            dt = time.perf_counter() - t
-            rates.append(oracle.component_edges(g, d) / dt)
-        rates = np.array(rates)
-        result["cpu_baseline_all_cores"] = {
-            "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
-            "unit": "GTEPS", "cores": oracle.threads(), "kind": "oracle",
-            "cpu": cpu_model(),
-            "sample": f"the same {len(sample)} roots: level-synchronous top-down OpenMP BFS "
-                      f"(distances), {time.perf_counter() - t_all:.1f}s total",
-        }
+        cpu_leg(args, e, roots, result, checks)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def _check_roots(oracle, g, roots, dist, parent, iterations, pool):
+    """Roots whose distances (and parents, iteration counts where given)
+    differ from the oracle's queue BFS and max-ID parent pass."""
+    def one(i):
+        r = int(roots[i])
+        d = oracle.bfs(g, r)
+        ok = np.array_equal(dist[i], d)
+        if parent is not None:
+            ok = ok and np.array_equal(parent[i], oracle.parents_max(g, r, d))
+        if iterations is not None:
+            ok = ok and int(iterations[i]) == int(d.max()) + 1
+        return ok
+    return [int(roots[i]) for i, ok in enumerate(pool.map(one, range(len(roots)))) if not ok]
+
+
+def cpu_leg(args, e, roots, result, checks) -> None:
+    """The CPU leg: the oracle timed on a bounded sample of the headline
+    workload (cpu_baseline, one thread; cpu_baseline_all_cores), then every
+    timed output kept in `checks` compared element by element with it
+    (validated): all headline roots, all 64 batched slots of R-MAT s21 and
+    two slots of each of the 256 Erdos-Renyi graphs."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    t = time.perf_counter()
+    g = oracle.csr_from_edgelist(e)
+    log(f"oracle CSR in {time.perf_counter() - t:.1f}s")
+    sample = roots[: args.cpu_roots]
+    rates = []
+    t_all = time.perf_counter()
+    for r in sample:
+        t = time.perf_counter()
+        d = oracle.bfs(g, int(r))
+        oracle.parents_max(g, int(r), d)
+        dt = time.perf_counter() - t
+        rates.append(oracle.component_edges(g, d) / dt)
+    cpu_s = time.perf_counter() - t_all
+    rates = np.array(rates)
+    result["cpu_baseline"] = {
+        "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
+        "unit": "GTEPS", "cores": 1, "kind": "oracle",
+        "sample": f"{len(sample)} of the {len(roots)} roots: FIFO-queue BFS + max-ID parent "
+                  f"pass (the sel-max outputs), 1 thread, {cpu_s:.1f}s total",
+    }
+    # the level-synchronous OpenMP oracle on all host threads (distances)
+    rates = []
+    t_all = time.perf_counter()
+    for r in sample:
+        t = time.perf_counter()
+        d = oracle.bfs_omp(g, int(r))
+        dt = time.perf_counter() - t
+        rates.append(oracle.component_edges(g, d) / dt)
+    rates = np.array(rates)
+    result["cpu_baseline_all_cores"] = {
+        "value": round(float(len(rates) / np.sum(1.0 / rates) / 1e9), 5),
+        "unit": "GTEPS", "cores": oracle.threads(), "kind": "oracle",
+        "cpu": cpu_model(),
+        "sample": f"the same {len(sample)} roots: level-synchronous top-down OpenMP BFS "
+                  f"(distances), {time.perf_counter() - t_all:.1f}s total",
+    }
+    # validation of the timed outputs (the oracle calls release the GIL, so a
+    # thread pool runs them in parallel)
+    t = time.perf_counter()
+    report, bad = {}, []
+    with ThreadPoolExecutor(max_workers=16) as pool:
+        for (ee, rr, res) in checks.get("headline", []):
+            par = res.parent.cpu().numpy() if res.parent is not None else None
+            wrong = _check_roots(oracle, g, rr, res.dist.cpu().numpy(), par, res.iterations, pool)
+            report["headline_roots"] = int(len(rr))
+            bad += [("headline", r) for r in wrong]
+        del g
+        for (ee, rr, dist) in checks.get("batched_rmat_s21", []):
+            gb = oracle.csr_from_edgelist(ee)
+            wrong = _check_roots(oracle, gb, rr, dist, None, None, pool)
+            report["batched_rmat_s21_slots"] = int(len(rr))
+            bad += [("batched_rmat_s21", r) for r in wrong]
+            del gb
+        n_er = 0
+        for (ee, rr, dist) in checks.get("batched_er_256", []):
+            gi = oracle.csr_from_edgelist(ee)
+            wrong = _check_roots(oracle, gi, rr, dist, None, None, pool)
+            n_er += len(rr)
+            bad += [("batched_er_256", ee.name, r) for r in wrong]
+        if n_er:
+            report["batched_er_256_slots"] = n_er
+    forms_ok = all(f.get("same_outputs", True) for f in result.get("forms", {}).values())
+    for case in result.get("learned_schedule", {}).values():
+        if isinstance(case, dict) and "ms_per_bfs" in case:
+            forms_ok = forms_ok and case["ms_per_bfs"].get("forms_agree", True)
+    report["other_forms_equal_to_checked_outputs"] = bool(forms_ok)
+    report["mismatches"] = [list(map(str, b)) for b in bad[:16]]
+    report["seconds"] = round(time.perf_counter() - t, 1)
+    result["validated"] = not bad and forms_ok
+    result["validation"] = report
+    log(f"validation: {report}")
 
 
 if __name__ == "__main__":

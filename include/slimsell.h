@@ -56,7 +56,7 @@ typedef enum {
 /* ------------------------------------------------------------------ layout */
 
 /*
- * Host-side SlimSell layout (Section III-B; Sell-C-sigma in Section II-C):
+ * Host-side SlimSell layout (Section III-B; Sell-C-sigma in Section II-D):
  *   rows are the vertices, sorted by decreasing degree inside windows of sigma
  *   consecutive original IDs (stable on the ID), then relabelled to their
  *   sorted position; chunk i holds rows [64 i, 64 i + 64).
@@ -266,7 +266,7 @@ typedef struct {
  * this mode; a barrier that waits more than 5 s is reported as SS_EHIP. */
 #define SS_RUN_PERSISTENT 4
 /* Comparator: run the levels on Sell-C-sigma instead of SlimSell (Section
- * II-C, Table "sizes"): a val array (1 = edge, 0 = padding) is streamed beside
+ * II-D, Table "sizes"): a val array (1 = edge, 0 = padding) is streamed beside
  * a col array whose padding cells hold a valid row, so each cell costs 8 bytes
  * instead of 4.  Built on the device at first use (2 x 4 B per cell).  Same
  * results; single-root levels only (no schedule, no persistent launch). */
@@ -353,7 +353,7 @@ typedef struct {
  *               unreachable.  SS_SELMAX yields it from the product itself;
  *               the other semirings run the DP transformation
  *               (slimsell_dp_parents) after each root's BFS, inside the
- *               timed region (Section II-B; "DP" vs "No-DP").
+ *               timed region (Section II-C; "DP" vs "No-DP").
  *   real_val  : device float[num_roots * n] or NULL; SS_REAL only: the
  *               real-semiring value x_{d(v)}^v at discovery, i.e. the number
  *               of neighbours one level closer (root 1, unreachable 0).
@@ -364,7 +364,7 @@ int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiri
                  const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
 
 /*
- * DP transformation (Section II-B): parents from BFS distances.  For every
+ * DP transformation (Section II-C): parents from BFS distances.  For every
  * vertex v with dist[v] >= 1, parent[v] = the largest original ID u among
  * v's neighbours with dist[u] = dist[v] - 1 (-1 if there is none); a vertex
  * with dist 0 is its own parent; dist < 0 gives -1.  One sweep of the
@@ -416,7 +416,10 @@ int slimsell_sched_load(const float* weights, int64_t count);
 /* Remove the model (learned scheduling then uses the fixed heuristic). */
 int slimsell_sched_clear(void);
 /* Per-level record of the last scheduled run on g: host float[cap][12] =
- * 6 features, 4 scores (0 without a model), chosen variant, level. */
+ * 6 features, 4 scores (0 without a model), chosen variant, level.  *levels
+ * receives the records written: the last scheduled run's level count (its
+ * iterations, at most min(n + 2, 65536)), clamped to cap; 0 before any
+ * scheduled run. */
 int slimsell_sched_log(const ss_graph* g, float* out, int32_t cap, int32_t* levels);
 
 /*

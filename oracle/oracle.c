@@ -12,13 +12,13 @@
  *
  * Contents
  *   oracle_csr            canonical simple undirected graph as sorted CSR
- *                         (Section II-C, "Adjacency List (AL)")
+ *                         (Section II-D, "Adjacency List (AL)")
  *   oracle_bfs            textbook FIFO-queue BFS distances
- *                         (Section II-B, "Traditional BFS")
+ *                         (Section II-C, "Traditional BFS")
  *   oracle_bfs_omp        the same distances by a level-synchronous top-down
  *                         sweep on all host cores (CPU baseline only)
  *   oracle_parents_max    the DP transformation p = DP(d) with the largest
- *                         qualifying neighbour as the parent (Section II-B)
+ *                         qualifying neighbour as the parent (Section II-C)
  *   oracle_real_counts    number of neighbours one level closer to the root
  *   oracle_lneg           the paper's logical negation of a vector (Section
  *                         II-A, "Linear Algebra")
@@ -56,7 +56,7 @@ static int cmp_i32(const void* a, const void* b) {
 }
 
 /*
- * Canonical simple undirected graph (Section II-C, "Adjacency List (AL)"): every
+ * Canonical simple undirected graph (Section II-D, "Adjacency List (AL)"): every
  * tuple (u, v) with u != v contributes both directions; self-loops are dropped
  * and repeated neighbours are kept once.  rowptr has n+1 entries; adj must hold
  * 2m entries (an upper bound).  Returns the number of directed entries E, or <0.
@@ -103,7 +103,7 @@ int64_t oracle_csr(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
 }
 
 /*
- * Textbook BFS (Section II-B, "Traditional BFS"): a FIFO queue; a vertex gets
+ * Textbook BFS (Section II-C, "Traditional BFS"): a FIFO queue; a vertex gets
  * distance d+1 when it is first seen from a vertex at distance d.  Unreached
  * vertices keep -1.  Returns the number of reached vertices.
  */
@@ -173,7 +173,7 @@ int32_t oracle_bfs_omp(const int64_t* rowptr, const int32_t* adj, int32_t n, int
 }
 
 /*
- * DP transformation (Section II-B): for every reached v other than the root,
+ * DP transformation (Section II-C): for every reached v other than the root,
  * its parent is a neighbour w with d(w) = d(v) - 1.  Among several such
  * neighbours the largest ID is taken.  parent[root] = root, unreached = -1.
  */

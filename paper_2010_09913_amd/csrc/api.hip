@@ -956,15 +956,18 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     if (rc) return rc;
     if (plan.schedule && (rc = launch_sched_init(g, g.ws, g.h_perm[roots[r]], st))) return rc;
     LevelArgs a = base_args(g, plan, o, run, r);
+    if (plan.schedule) g.ws.sched_log_levels = 0;  // the log is rewritten by this run
     rc = run_levels(g, plan, (int)s, a, g.ws.vec_a, g.ws.vec_b, st, &log, r);
     if (rc) return rc;
+    if (plan.schedule)
+      g.ws.sched_log_levels = std::min<int64_t>(log.iters[r], g.ws.sched_log_cap);
     if (o->iterations_out) o->iterations_out[r] = log.iters[r];
     int32_t* dist_r = dist + (int64_t)r * g.n;
     int32_t* parent_r = parent ? parent + (int64_t)r * g.n : nullptr;
     rc = launch_finalise(s, g, g.ws, dist_r, s == SS_SELMAX ? parent_r : nullptr,
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
-    // the other semirings get parents by the DP transformation (Section II-B)
+    // the other semirings get parents by the DP transformation (Section II-C)
     if (parent_r && s != SS_SELMAX &&
         (rc = launch_dp(g, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r, parent_r,
                         st)))
@@ -1055,7 +1058,7 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
 
 int slimsell_sched_log(const ss_graph* g, float* out, int32_t cap, int32_t* levels) {
   if (!g || !out || cap < 0) return set_error(SS_EINVAL, "bad argument");
-  const int64_t nl = std::min<int64_t>(cap, g->ws.sched_log_cap);
+  const int64_t nl = std::min<int64_t>(cap, g->ws.sched_log_levels);
   if (nl > 0)
     SS_HIP(hipMemcpy(out, g->ws.sched_log, sizeof(float) * (size_t)nl * 12, hipMemcpyDeviceToHost));
   if (levels) *levels = (int32_t)nl;

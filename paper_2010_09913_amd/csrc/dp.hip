@@ -1,4 +1,4 @@
-// DP transformation on the GPU (Section II-B): parents from distances.
+// DP transformation on the GPU (Section II-C): parents from distances.
 //
 // For a reached vertex v other than the root, its parent is a neighbour one
 // level closer to the root; the largest such original ID is taken (the

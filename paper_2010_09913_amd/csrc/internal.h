@@ -84,6 +84,7 @@ struct Workspace {
   double* sched_sums = nullptr;        // [8] running totals for the features, 2 buffers
   float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
   int64_t sched_log_cap = 0;
+  int64_t sched_log_levels = 0;        // levels the last scheduled run recorded
   float* model = nullptr;              // [kModelCap] device copy of the scheduler model
   uint64_t model_version = 0;          // version of the process model copied there
   int2* segs = nullptr;                 // push segments: capacity seg_cap

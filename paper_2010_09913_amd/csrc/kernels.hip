@@ -1,7 +1,7 @@
 // HIP kernels of one SlimSell BFS on gfx950 (CDNA4).
 //
 // One chunk of 64 rows is one 64-lane wavefront: lane = row inside the chunk,
-// so the column-major chunk layout (Section II-C, Sell-C-sigma) turns every
+// so the column-major chunk layout (Section II-D, Sell-C-sigma) turns every
 // column step into one coalesced 256-byte load of `col`.  A padding cell
 // (-1, Section III-B) exec-masks its lane: no gather, no contribution.
 //
@@ -324,7 +324,7 @@ struct Batch {
 // mode 2; modes 0 and 1 compute every term); `cols` receives the columns the
 // lane loaded.
 //
-// VAL (the Sell-C-sigma comparator of Section II-C): a second stream, val,
+// VAL (the Sell-C-sigma comparator of Section II-D): a second stream, val,
 // runs beside col and decides whether a cell is an edge (1) or padding (0);
 // the padding cells of that col hold a valid row, so only val marks them.
 template <class S, int U, bool STAGED, bool VAL = false>
@@ -714,7 +714,7 @@ __global__ void persistent_kernel(LevelArgs a, void* buf_a, void* buf_b, int32_t
 // ------------------------------------------------------------ push levels ---
 //
 // The same product computed from the frontier side (the sparse-vector form
-// of Section II-B): every row u of the previous level's frontier queue offers
+// of Section II-C): every row u of the previous level's frontier queue offers
 // its term to each neighbour w that is still live, through the semiring's
 // atomic; the first offer to w claims it for this level's queue.  A second
 // kernel then post-processes the claimed rows.  Since A is symmetric, row u's

@@ -1,6 +1,6 @@
 // Host construction of the SlimSell layout (Section III-B, "Reducing Storage
 // Complexity with SlimSell"; the Sell-C-sigma layout it derives from is in
-// Section II-C).  Multithreaded with std::thread; deterministic for any thread
+// Section II-D).  Multithreaded with std::thread; deterministic for any thread
 // count because every row's neighbour list is sorted before use.
 //
 // Steps

@@ -1,4 +1,4 @@
-"""GPU tests of the DP transformation (parents from distances, Section II-B):
+"""GPU tests of the DP transformation (parents from distances, Section II-C):
 bit-exact against the oracle's max-ID parents for every semiring, every
 split length (pieces combine by atomicMax) and distances from the batched
 SpMM."""

@@ -1,5 +1,5 @@
 """GPU tests of the Sell-C-sigma comparator (a val array streamed beside col,
-Section II-C): results bit-identical to the oracle and to SlimSell."""
+Section II-D): results bit-identical to the oracle and to SlimSell."""
 import sys
 
 import numpy as np

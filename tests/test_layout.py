@@ -1,4 +1,4 @@
-"""Host SlimSell layout: the invariants of Sections II-C and III-B.
+"""Host SlimSell layout: the invariants of Sections II-D and III-B.
 
 L1 rows hold exactly their neighbour sets (relabelled), L2 the cell counts of
 Table "sizes", L3 the padding bound of the work analysis (Section III-A,
