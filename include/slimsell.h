@@ -364,6 +364,35 @@ int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiri
                  const ss_bfs_opts* opts, int32_t* dist, int32_t* parent, float* real_val);
 
 /*
+ * Allocation-free BFS, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation, arguments, outputs and errors of slimsell_bfs,
+ * with the per-call workspace (frontier vectors, row states, distances,
+ * SlimChunk combine buffers, level tags, frontier summaries) in one fixed
+ * 64 MiB device array that the library holds on every GPU it runs on until
+ * the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call; outputs are the caller's.
+ *   Scratch needed: 8 KiB + 4 B per chunk + the frontier summaries (at most
+ *   32 KiB) + per row: tropical 8 B (16.25 B with parents), real 21 B,
+ *   boolean 11 B, sel-max 13.25 B; more than 64 MiB is SS_EINVAL (sel-max
+ *   fits about 5 million rows).
+ *   opts   : slimwork, split_len, waves_per_group, max_levels, stream and
+ *            iterations_out as slimsell_bfs; flags 0 or SS_NO_SUMMARY;
+ *            schedule 0; level_stats_out and run_stats_out NULL (anything
+ *            else is SS_EINVAL).  split_len must name a configuration whose
+ *            work units exist: the graph's own (split_len = -1; prepared by
+ *            slimsell_build and slimsell_tune_set) or one an earlier
+ *            slimsell_bfs call used; otherwise SS_EINVAL.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (a call initialises everything it reads): calls that overlap on
+ * one GPU race, whatever their graphs or streams.  The graph's level-report
+ * ring is used as in slimsell_bfs, so calls on one graph must not overlap.
+ */
+int slimsell_bfs_noalloc(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiring s,
+                         const ss_bfs_opts* opts, int32_t* dist, int32_t* parent,
+                         float* real_val);
+
+/*
  * DP transformation (Section II-C): parents from BFS distances.  For every
  * vertex v with dist[v] >= 1, parent[v] = the largest original ID u among
  * v's neighbours with dist[u] = dist[v] - 1 (-1 if there is none); a vertex

@@ -218,7 +218,7 @@ class Graph:
             level_cap: int = 0, timing: bool = False, counters: bool = None,
             persistent: bool = False, want_parent: bool = True, want_real: bool = True,
             dp: bool = False, sell: bool = False, summary: bool = True, dist=None,
-            parent=None, real_val=None) -> BfsResult:
+            parent=None, real_val=None, no_alloc: bool = False) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
         Sel-max returns parents (unless want_parent=False); dp=True gives the
@@ -227,7 +227,9 @@ class Graph:
         summary=False turns off the frontier-summary filter of the gathers.
         level_cap > 0 records per-level statistics (fused counters unless
         counters=False); timing=True adds event timings per level and per root,
-        timing="bfs" per root only.
+        timing="bfs" per root only.  no_alloc=True calls the allocation-free
+        entry point (slimsell_bfs_noalloc: no statistics, schedule, persistent
+        launch or comparator; pass preallocated outputs to allocate nothing).
         """
         import torch
         s = _semiring(semiring)
@@ -275,8 +277,9 @@ class Graph:
         def ptr(t):
             return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
 
-        check(_native.load().slimsell_bfs(self._h, _p32(roots), nr, s, ctypes.byref(o),
-                                          ptr(dist), ptr(parent), ptr(real_val)))
+        fn = _native.load().slimsell_bfs_noalloc if no_alloc else _native.load().slimsell_bfs
+        check(fn(self._h, _p32(roots), nr, s, ctypes.byref(o), ptr(dist), ptr(parent),
+                 ptr(real_val)))
         levels = run_d = None
         if lvl is not None:
             levels = _records(lvl, _LEVEL_DTYPE, (nr, level_cap))

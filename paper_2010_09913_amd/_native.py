@@ -28,6 +28,7 @@ EXPORTS = [
     "slimsell_build_multi", "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
     "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log", "slimsell_sched_grad",
     "slimsell_sched_forward", "slimsell_sched_train", "slimsell_dp_parents",
+    "slimsell_bfs_noalloc",
 ]
 SCHED_PARAMS, SCHED_FEATURES, SCHED_VARIANTS = 1412, 6, 4
 
@@ -130,6 +131,8 @@ def load() -> ctypes.CDLL:
     lib.slimsell_free.restype = None
     lib.slimsell_bfs.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(BfsOpts), vp, vp, vp]
+    lib.slimsell_bfs_noalloc.argtypes = [vp, c_i32p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(BfsOpts), vp, vp, vp]
     lib.slimsell_sync.argtypes = [vp]
     lib.slimsell_build_multi.argtypes = [ctypes.c_int32, c_i64p, c_i32p, c_i32p, c_i32p,
                                          ctypes.c_int32, ctypes.c_int32, vp, vpp]
@@ -158,7 +161,7 @@ def load() -> ctypes.CDLL:
                  "slimsell_graph_parts", "slimsell_bfs_batch", "slimsell_autotune",
                  "slimsell_sched_load", "slimsell_sched_clear", "slimsell_sched_log",
                  "slimsell_sched_grad", "slimsell_sched_forward", "slimsell_sched_train",
-                 "slimsell_dp_parents"):
+                 "slimsell_dp_parents", "slimsell_bfs_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -97,14 +97,20 @@ static void release_graph(Graph* g) {
 // Work units for split length `split` (0 = never split) with small chunks
 // packed into runs of at most `pack` columns (0 = one chunk per unit).
 // Chunks without columns are left out: their rows have no neighbours, so no
-// product can change them and no gather reads them.
-static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out) {
+// product can change them and no gather reads them.  Built and uploaded on
+// first use; with `lookup_only` a missing list is an error instead.
+static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
+                     bool lookup_only = false) {
   auto key = std::make_pair(split, pack);
   auto it = g.units.find(key);
   if (it != g.units.end()) {
     *out = &it->second;
     return SS_OK;
   }
+  if (lookup_only)
+    return set_error(SS_EINVAL, "no work units prepared for split_len " + std::to_string(split) +
+                                    ", pack_cols " + std::to_string(pack) +
+                                    " (slimsell_tune_set prepares the graph's configuration)");
   constexpr int32_t kMaxRun = 64;
   std::vector<Unit> units;
   std::vector<int32_t> pieces((size_t)g.n_chunks, 1);
@@ -305,9 +311,17 @@ struct RunLog {
   std::vector<int32_t> iters;
 };
 
+// With `no_alloc`, only what allocates nothing is accepted: no statistics,
+// schedule, persistent launch or Sell-C-sigma comparator, and work units that
+// already exist.
 static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
-                    int64_t default_cap, hipStream_t st, RunPlan* p) {
+                    int64_t default_cap, hipStream_t st, RunPlan* p, bool no_alloc = false) {
   if (o->size != sizeof(ss_bfs_opts)) return set_error(SS_EINVAL, "opts->size mismatch");
+  if (no_alloc && ((o->flags & ~SS_NO_SUMMARY) || o->schedule || o->level_stats_out ||
+                   o->run_stats_out))
+    return set_error(SS_EINVAL,
+                     "the allocation-free BFS takes no statistics, schedule, persistent launch "
+                     "or comparator (flags may hold SS_NO_SUMMARY only)");
   if (o->slimwork < 0 || o->slimwork > 2) return set_error(SS_EINVAL, "slimwork must be 0, 1 or 2");
   p->waves = o->waves_per_group ? o->waves_per_group : g.tune.waves_per_group;
   if (p->waves != 1 && p->waves != 2 && p->waves != 4 && p->waves != 8 && p->waves != 16)
@@ -378,7 +392,7 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   }
   if (o->schedule && o->slimwork != 2) return set_error(SS_EINVAL, "scheduling needs slimwork = 2");
   p->schedule = o->schedule;
-  int rc = get_units(g, split, pack, &p->ul);
+  int rc = get_units(g, split, pack, &p->ul, no_alloc);
   if (rc) return rc;
   if (p->schedule) {
     const int32_t vsplit[kPullVariants] = {0, 256, 1024};
@@ -421,8 +435,8 @@ static int mark_event(Graph& g, const RunPlan& p, size_t& next_ev, hipStream_t s
   return SS_OK;
 }
 
-static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uint32_t run,
-                           int32_t run_idx) {
+static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, const ss_bfs_opts* o,
+                           uint32_t run, int32_t run_idx) {
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.col = p.sell ? g.d_scol : g.d_col;
@@ -434,21 +448,21 @@ static LevelArgs base_args(Graph& g, const RunPlan& p, const ss_bfs_opts* o, uin
   a.units = p.ul->d_units;
   a.pieces = p.ul->d_pieces;
   a.n_units = p.ul->count;
-  a.state = g.ws.state;
-  a.g = g.ws.g;
-  a.d = g.ws.d;
-  a.rv = g.ws.rv;
-  a.acc = g.ws.acc;
-  a.arrive = g.ws.arrive;
-  a.any = g.ws.any;
+  a.state = ws.state;
+  a.g = ws.g;
+  a.d = ws.d;
+  a.rv = ws.rv;
+  a.acc = ws.acc;
+  a.arrive = ws.arrive;
+  a.any = ws.any;
   a.counters = p.counting ? g.ws.counters + p.words_per_run * run_idx : nullptr;
   a.report = g.ws.d_report;
   a.run_id = run;
   a.n_pad = (uint32_t)g.n_pad;
   a.slimwork = p.slimwork;
   a.lds_bytes = p.lds_bytes;
-  a.summ = p.summ ? g.ws.summ : nullptr;
-  a.summ_words = g.ws.summ_words;
+  a.summ = p.summ ? ws.summ : nullptr;
+  a.summ_words = ws.summ_words;
   a.filter_limit = p.filter_limit;
   if (p.schedule) {
     a.variant = g.ws.variant;
@@ -714,6 +728,99 @@ static int ensure_batch_workspace(Graph& g, int64_t roots,
   return SS_OK;
 }
 
+
+// ------------------------------------------------ allocation-free BFS state
+//
+// slimsell_bfs_noalloc keeps the per-call BFS workspace (frontier vectors,
+// row states, distances, SlimChunk combine buffers, level tags, frontier
+// summaries) in one file-scope device array instead of the graph's
+// workspace, so a call allocates nothing.  Every GPU the library runs on
+// holds its own copy for the life of the process; host code uses only the
+// address hipGetSymbolAddress returns for the current device, never the
+// array's name (which is a host-side stand-in).
+constexpr int64_t kScratchBytes = 64ll << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices];
+
+// Address of this device's scratch, looked up once per device (the device
+// must be current).
+static int scratch_address(int device, uint8_t** out) {
+  if (device < 0 || device >= kScratchDevices)
+    return set_error(SS_EUNSUP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_error(SS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<uint8_t*>(g_scratch_ptr[device]);
+  return SS_OK;
+}
+
+// The workspace of one allocation-free call on graph g, carved from `base` in
+// 256-byte aligned pieces (base == nullptr: sizes only).  Only the buffers
+// the semiring touches are carved (the DP transformation adds distances and
+// their codes); returns the bytes used.
+static int64_t carve_workspace(const Graph& g, int semiring, bool dp, uint8_t* base,
+                               Workspace* w) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += (std::max<int64_t>(bytes, 1) + 255) / 256 * 256;
+    return p;
+  };
+  const int64_t n = g.n_pad, nc = std::max<int64_t>(g.n_chunks, 1);
+  *w = Workspace();
+  w->n_pad = n;
+  w->any = static_cast<uint64_t*>(take(8 * (int64_t)kRing));
+  w->arrive = static_cast<int32_t*>(take(4 * nc));
+  if (g.ws.summ) {
+    w->summ = static_cast<uint32_t*>(take(4 * (3 * (int64_t)g.ws.summ_words + 4)));
+    w->summ_words = g.ws.summ_words;
+  }
+  w->acc = static_cast<int32_t*>(take(4 * n));
+  switch (semiring) {
+    case SS_TROPICAL:
+      w->state = static_cast<int32_t*>(take(4 * n));
+      break;
+    case SS_REAL:
+      w->vec_a = take(4 * n);
+      w->vec_b = take(4 * n);
+      w->g = static_cast<uint8_t*>(take(n));
+      w->d = static_cast<int32_t*>(take(4 * n));
+      w->rv = static_cast<float*>(take(4 * n));
+      break;
+    case SS_BOOLEAN:
+      w->vec_a = take(n);
+      w->vec_b = take(n);
+      w->g = static_cast<uint8_t*>(take(n));
+      w->d = static_cast<int32_t*>(take(4 * n));
+      break;
+    default:  // SS_SELMAX: one 64-bit frontier word per chunk
+      w->vec_a = take(8 * nc);
+      w->vec_b = take(8 * nc);
+      w->state = static_cast<int32_t*>(take(4 * n));
+      w->g = static_cast<uint8_t*>(take(n));
+      w->d = static_cast<int32_t*>(take(4 * n));
+      break;
+  }
+  if (dp && semiring == SS_TROPICAL) {
+    // row distances and their 2-bit codes (n / 4 bytes); the other
+    // semirings have both buffers already
+    w->d = static_cast<int32_t*>(take(4 * n));
+    w->g = static_cast<uint8_t*>(take(n / 4));
+  }
+  // the graph's host-mapped report ring (part of the graph, not scratch)
+  w->h_report = g.ws.h_report;
+  w->d_report = g.ws.d_report;
+  return off;
+}
+
 }  // namespace ss
 
 using namespace ss;
@@ -857,6 +964,13 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
     if (ee != hipSuccess) rc = hip_fail(ee, "upload layout");
   }
   if (!rc) rc = alloc_workspace(*g);
+  if (!rc) {
+    // the default configuration's work units (the allocation-free BFS needs them)
+    UnitList* ul = nullptr;
+    const int32_t sp = g->tune.split_len;
+    const int32_t pack = g->tune.pack_cols < 0 ? (sp > 0 ? sp : 0) : g->tune.pack_cols;
+    rc = get_units(*g, g->tune.split_len, pack, &ul);
+  }
   if (!rc) rc = dalloc(&g->d_voff, 2);
   if (!rc && hipMemcpy(g->d_voff, g->h_voff.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice) !=
                  hipSuccess)
@@ -906,7 +1020,12 @@ int slimsell_tune_set(ss_graph* g, const ss_tune* t) {
     return set_error(SS_EINVAL, "lds_kib must be 0, 16, 32 or 64");
   std::lock_guard<std::mutex> lock(g->mu);
   g->tune = *t;
-  return SS_OK;
+  // the work units of the configuration, so that the allocation-free BFS
+  // finds them
+  SS_HIP(hipSetDevice(g->device));
+  UnitList* ul = nullptr;
+  const int32_t sp = t->split_len;
+  return get_units(*g, sp, t->pack_cols < 0 ? (sp > 0 ? sp : 0) : t->pack_cols, &ul);
 }
 
 int slimsell_tune_get(const ss_graph* g, ss_tune* t) {
@@ -955,7 +1074,7 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     rc = launch_init(s, g, g.ws, g.h_perm[roots[r]], plan.summ, st);
     if (rc) return rc;
     if (plan.schedule && (rc = launch_sched_init(g, g.ws, g.h_perm[roots[r]], st))) return rc;
-    LevelArgs a = base_args(g, plan, o, run, r);
+    LevelArgs a = base_args(g, g.ws, plan, o, run, r);
     if (plan.schedule) g.ws.sched_log_levels = 0;  // the log is rewritten by this run
     rc = run_levels(g, plan, (int)s, a, g.ws.vec_a, g.ws.vec_b, st, &log, r);
     if (rc) return rc;
@@ -969,8 +1088,8 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     if (rc) return rc;
     // the other semirings get parents by the DP transformation (Section II-C)
     if (parent_r && s != SS_SELMAX &&
-        (rc = launch_dp(g, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r, parent_r,
-                        st)))
+        (rc = launch_dp(g, g.ws, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
+                        parent_r, st)))
       return rc;
     if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
   }
@@ -993,7 +1112,7 @@ int slimsell_dp_parents(ss_graph* gp, const int32_t* dist, int32_t num_roots, in
   int rc = get_units(g, split, pack, &ul);
   if (rc) return rc;
   for (int32_t r = 0; r < num_roots; ++r) {
-    rc = launch_dp(g, *ul, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
+    rc = launch_dp(g, g.ws, *ul, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
                    dist + (int64_t)r * g.n, parent + (int64_t)r * g.n, st);
     if (rc) return rc;
   }
@@ -1042,7 +1161,7 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
   if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_first[0]))) return rc;
   rc = launch_batch_init(g, bw, (int32_t)root_rows.size(), plan.summ, st);
   if (rc) return rc;
-  LevelArgs a = base_args(g, plan, o, run, 0);
+  LevelArgs a = base_args(g, g.ws, plan, o, run, 0);
   a.acc64 = bw.acc64;
   a.vis = bw.vis;
   a.full = bw.full;
@@ -1128,6 +1247,58 @@ int slimsell_build_multi(int32_t num_graphs, const int64_t* edge_offsets, const 
     rc = set_error(SS_EHIP, "upload graph offsets");
   if (rc) { slimsell_free(g); return rc; }
   *out = g;
+  return SS_OK;
+}
+
+int slimsell_bfs_noalloc(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semiring s,
+                         const ss_bfs_opts* o, int32_t* dist, int32_t* parent, float* real_val) {
+  if (!gp) return set_error(SS_EINVAL, "graph is NULL");
+  Graph& g = *gp;
+  if (num_roots < 0) return set_error(SS_EINVAL, "num_roots < 0");
+  if (num_roots == 0) return SS_OK;
+  if (!roots || !dist) return set_error(SS_EINVAL, "roots and dist are required");
+  if ((int)s < 0 || (int)s > 3) return set_error(SS_EINVAL, "unknown semiring");
+  if (real_val && s != SS_REAL) return set_error(SS_EINVAL, "real_val needs SS_REAL");
+  for (int32_t r = 0; r < num_roots; ++r)
+    if (roots[r] < 0 || roots[r] >= g.n) return set_error(SS_EINVAL, "root out of range [0, n)");
+  const bool dp = parent && s != SS_SELMAX;
+  Workspace w;
+  const int64_t need = carve_workspace(g, (int)s, dp, nullptr, &w);
+  if (need > kScratchBytes)
+    return set_error(SS_EINVAL, "the allocation-free BFS needs " + std::to_string(need) +
+                                    " bytes of scratch for this graph and semiring; the limit is " +
+                                    std::to_string(kScratchBytes));
+  ss_bfs_opts def = default_opts();
+  if (!o) o = &def;
+  std::lock_guard<std::mutex> lock(g.mu);
+  SS_HIP(hipSetDevice(g.device));
+  uint8_t* base = nullptr;
+  int rc = scratch_address(g.device, &base);
+  if (rc) return rc;
+  (void)carve_workspace(g, (int)s, dp, base, &w);
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  RunPlan plan;
+  if ((rc = plan_run(g, o, (int)s, num_roots, (int64_t)g.n + 1, st, &plan, true))) return rc;
+  // level tags carry the graph's run counter, and other graphs share this
+  // scratch: start from a clean ring (a fill kernel, not a memset node)
+  if ((rc = launch_fill_u64(reinterpret_cast<unsigned long long*>(w.any), 0ull, kRing, st)))
+    return rc;
+  RunLog log((size_t)num_roots);
+  for (int32_t r = 0; r < num_roots; ++r) {
+    const uint32_t run = next_run_id(g);
+    if ((rc = launch_init(s, g, w, g.h_perm[roots[r]], plan.summ, st))) return rc;
+    LevelArgs a = base_args(g, w, plan, o, run, r);
+    if ((rc = run_levels(g, plan, (int)s, a, w.vec_a, w.vec_b, st, &log, r))) return rc;
+    if (o->iterations_out) o->iterations_out[r] = log.iters[r];
+    int32_t* dist_r = dist + (int64_t)r * g.n;
+    int32_t* parent_r = parent ? parent + (int64_t)r * g.n : nullptr;
+    rc = launch_finalise(s, g, w, dist_r, s == SS_SELMAX ? parent_r : nullptr,
+                         real_val ? real_val + (int64_t)r * g.n : nullptr, st);
+    if (rc) return rc;
+    if (dp && (rc = launch_dp(g, w, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
+                              parent_r, st)))
+      return rc;
+  }
   return SS_OK;
 }
 

@@ -151,10 +151,9 @@ __global__ void dp_finalise_kernel(int32_t n_pad, const int32_t* v, const int32_
   parent[o] = d == 0 ? o : ((d > 0 && best > 0) ? best - 1 : -1);
 }
 
-int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t max_groups,
-              const int32_t* dist, int32_t* parent, void* stream) {
+int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unroll, int waves,
+              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Workspace& ws = g.ws;
   const unsigned rows_blocks = (unsigned)((g.n_pad + 255) / 256);
   dp_prep_kernel<<<rows_blocks, 256, 0, st>>>((int32_t)g.n_pad, g.d_v, dist, ws.d, ws.g, ws.acc);
   int rc = check_launch("dp_prep_kernel");

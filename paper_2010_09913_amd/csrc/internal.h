@@ -278,9 +278,10 @@ int launch_persistent(int semiring, int unroll, const LevelArgs& a, void* buf_a,
 int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
                        const LevelArgs& a, const SchedLaunch& p, void* stream);
 // DP transformation (dp.hip): parents (original IDs) from distances (original
-// IDs) of one root, through the workspace's d, g and acc buffers.
-int launch_dp(const Graph& g, const UnitList& ul, int unroll, int waves, int64_t max_groups,
-              const int32_t* dist, int32_t* parent, void* stream);
+// IDs) of one root, through the workspace's d (4 B per row), g (n_pad / 4
+// bytes of codes) and acc (4 B per row) buffers.
+int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unroll, int waves,
+              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, bool summary,
                 void* stream);
