@@ -37,8 +37,19 @@ TEST_BYTES = {"tropical": 4, "real": 1, "boolean": 1, "selmax": 4}
 GATHER_BYTES = {"tropical": 4, "real": 4, "boolean": 1, "selmax": 4}
 
 
-PROFILE_JSON = os.path.join(ROOT, "profiles", "level_kernel_selmax_rmat_s22.json")
-PROFILE_MD = os.path.join(ROOT, "profiles", "level_kernel_selmax_rmat_s22.md")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+# profile summaries by kernel: (file base name, kernel-name substring in the
+# rocprofv3 trace, workload text)
+PROFILES = {
+    "level_kernel<selmax>": ("level_kernel_selmax_rmat_s22", "level_kernel<ss::SelMax",
+                             "R-MAT s22, 64 roots, sel-max, sigma = n"),
+    "level_kernel<batch>": ("level_kernel_batch_rmat_s21", "level_kernel<ss::Batch",
+                            "R-MAT s21, 64 roots in one boolean SpMM, sigma = n"),
+    "level_kernel<dp>": ("level_kernel_dp_rmat_s22", "level_kernel<ss::Dp",
+                         "R-MAT s22, DP transformation after tropical BFS, 16 roots"),
+    "push_kernels<selmax>": ("push_kernels_selmax_rmat_s22", "push_",
+                             "R-MAT s22, sel-max, forced push schedule, 16 roots"),
+}
 KERNEL_SOURCES = ["paper_2010_09913_amd/csrc/kernels.hip", "paper_2010_09913_amd/csrc/device.h",
                   "paper_2010_09913_amd/csrc/internal.h"]
 
@@ -53,10 +64,13 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
+    """HBM bytes per launch of `kernel` from its committed counter summary,
     or None when there is none or the kernel sources changed since."""
+    base = PROFILES.get(kernel, (None,))[0]
+    if base is None:
+        return None
     try:
-        with open(PROFILE_JSON) as f:
+        with open(os.path.join(PROFILE_DIR, base + ".json")) as f:
             prof = json.load(f)
     except (OSError, ValueError):
         return None
@@ -79,59 +93,65 @@ def _find(d, suffix):
 
 
 def profile_summary(args) -> int:
-    """Summarise rocprofv3 output (kernel trace, FETCH_SIZE, WRITE_SIZE of
-    the timed bench, and the same counters of a 1 GiB device copy that
-    calibrates them) into profiles/."""
-    match = "level_kernel<ss::SelMax"
+    """Summarise rocprofv3 output for one kernel (kernel trace, FETCH_SIZE and
+    WRITE_SIZE of the same command, and the same counters of a 1 GiB device
+    copy that calibrates them) into profiles/<kernel file>.{md,json}."""
+    kernel = args.kernel
+    base, match, workload = PROFILES[kernel]
     stats = _csv_rows(_find(args.trace, "_kernel_stats.csv"))
-    row = next(r for r in stats if match in r["Name"])
+    rows = [r for r in stats if match in r["Name"]]
+    calls = sum(int(r["Calls"]) for r in rows)
+    total_ns = sum(float(r["TotalDurationNs"]) for r in rows)
 
     def per_dispatch(d, counter, name_part):
-        rows = [r for r in _csv_rows(_find(d, "_counter_collection.csv"))
-                if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
-        return sum(float(r["Counter_Value"]) for r in rows) / len(rows), len(rows)
+        rr = [r for r in _csv_rows(_find(d, "_counter_collection.csv"))
+              if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return sum(float(r["Counter_Value"]) for r in rr) / len(rr), len(rr)
 
-    fetch_kib, n_f = per_dispatch(args.fetch, "FETCH_SIZE", match)
-    write_kib, n_w = per_dispatch(args.write, "WRITE_SIZE", match)
-    copy_f, _ = per_dispatch(args.copy_fetch, "FETCH_SIZE", "copyBuffer")
-    copy_w, _ = per_dispatch(args.copy_write, "WRITE_SIZE", "copyBuffer")
-    gib_kib = float(1 << 20)                  # the copy reads and writes 1 GiB
-    f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
-    traffic = (fetch_kib * f_scale + write_kib * w_scale) * 1024.0
-    prof = {
-        "kernel": "level_kernel<selmax>", "workload": "R-MAT s22, 64 roots, sel-max, sigma=n",
-        "source_hash": kernel_source_hash(), "calls": int(row["Calls"]),
-        "avg_duration_ns": float(row["AverageNs"]), "fetch_kib_per_dispatch": fetch_kib,
-        "write_kib_per_dispatch": write_kib, "dispatches_counted": [n_f, n_w],
-        "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
-        "fetch_scale": f_scale, "write_scale": w_scale,
-        "traffic_bytes_per_launch": traffic,
-    }
-    out_json = os.path.join(args.out_dir, os.path.basename(PROFILE_JSON))
-    out_md = os.path.join(args.out_dir, os.path.basename(PROFILE_MD))
+    prof = {"kernel": kernel, "workload": workload, "source_hash": kernel_source_hash(),
+            "calls": calls, "avg_duration_ns": total_ns / max(calls, 1),
+            "instances": [r["Name"][:90] for r in rows]}
+    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+        fetch_kib, n_f = per_dispatch(args.fetch, "FETCH_SIZE", match)
+        write_kib, n_w = per_dispatch(args.write, "WRITE_SIZE", match)
+        copy_f, _ = per_dispatch(args.copy_fetch, "FETCH_SIZE", "copyBuffer")
+        copy_w, _ = per_dispatch(args.copy_write, "WRITE_SIZE", "copyBuffer")
+        gib_kib = float(1 << 20)                  # the copy reads and writes 1 GiB
+        f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
+        prof.update(fetch_kib_per_dispatch=fetch_kib, write_kib_per_dispatch=write_kib,
+                    dispatches_counted=[n_f, n_w], copy_fetch_kib=copy_f, copy_write_kib=copy_w,
+                    fetch_scale=f_scale, write_scale=w_scale,
+                    traffic_bytes_per_launch=(fetch_kib * f_scale + write_kib * w_scale) * 1024.0)
     os.makedirs(args.out_dir, exist_ok=True)
-    with open(out_json, "w") as f:
+    with open(os.path.join(args.out_dir, base + ".json"), "w") as f:
         json.dump(prof, f, indent=1)
-    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:6]
-    lines = [
-        "# level_kernel<SelMax> on R-MAT s22 (64 roots, sel-max, sigma = n)", "",
-        "Commands (run from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
-        f"    {args.cmd_trace}", f"    {args.cmd_fetch}", f"    {args.cmd_write}",
-        f"    {args.cmd_copy_fetch}", f"    {args.cmd_copy_write}", "",
-        "Kernel trace (`--kernel-trace --stats`), top kernels by total time:", "",
-        "| Kernel | Calls | Average ns | Min ns | Max ns | % |", "|---|---|---|---|---|---|"]
+    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
+    cmds = [c for c in (args.cmd_trace, args.cmd_fetch, args.cmd_write, args.cmd_copy_fetch,
+                        args.cmd_copy_write) if c]
+    lines = [f"# {kernel} on {workload}", "",
+             "Commands (run from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", ""]
+    lines += [f"    {c}" for c in cmds]
+    lines += ["", "Kernel trace (`--kernel-trace --stats`), top kernels by total time:", "",
+              "| Kernel | Calls | Average ns | Min ns | Max ns | % |", "|---|---|---|---|---|---|"]
     for r in top:
         lines.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                      f"{r['MinNs']} | {r['MaxNs']} | {float(r['Percentage']):.1f} |")
-    lines += ["", "HBM counters per dispatch of the level kernel (KiB), and the copy probe "
-              "(1 GiB read + 1 GiB written per dispatch) that calibrates them:", "",
-              "| | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
-              f"| level kernel, per dispatch | {fetch_kib:.0f} | {write_kib:.0f} |",
-              f"| copy probe, per dispatch | {copy_f:.0f} | {copy_w:.0f} |",
-              f"| scale (1 GiB / copy reading) | {f_scale:.3f} | {w_scale:.3f} |", "",
-              f"Traffic per launch: {traffic / 1e6:.1f} MB (scaled fetch + write).  "
-              f"Kernel sources hash {prof['source_hash']}.", ""]
-    with open(out_md, "w") as f:
+    lines += ["", f"{kernel}: {calls} calls, average {prof['avg_duration_ns']:.0f} ns "
+              f"(all instances matching `{match}`)."]
+    if "traffic_bytes_per_launch" in prof:
+        lines += ["", "HBM counters per dispatch (KiB), and the copy probe (1 GiB read + 1 GiB "
+                  "written per dispatch) that calibrates them:", "",
+                  "| | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
+                  f"| {kernel}, per dispatch | {prof['fetch_kib_per_dispatch']:.0f} | "
+                  f"{prof['write_kib_per_dispatch']:.0f} |",
+                  f"| copy probe, per dispatch | {prof['copy_fetch_kib']:.0f} | "
+                  f"{prof['copy_write_kib']:.0f} |",
+                  f"| scale (1 GiB / copy reading) | {prof['fetch_scale']:.3f} | "
+                  f"{prof['write_scale']:.3f} |", "",
+                  f"Traffic per launch: {prof['traffic_bytes_per_launch'] / 1e6:.1f} MB "
+                  f"(scaled fetch + write)."]
+    lines += ["", f"Kernel sources hash {prof['source_hash']}.", ""]
+    with open(os.path.join(args.out_dir, base + ".md"), "w") as f:
         f.write("\n".join(lines))
     print(json.dumps(prof))
     return 0
@@ -330,10 +350,21 @@ def bench_scale20(ss, graphgen, torch) -> dict:
     return out
 
 
-def bench_dp(G, roots, torch) -> dict:
+def dp_bytes(runs, n_pad: int, nonempty: int, reached) -> np.ndarray:
+    """Algorithmic bytes of the DP transformation's sweep per root: col cells
+    streamed (4 B), per processed row its degree read and its best-v write
+    (8 B), cs + cl per processed chunk (8 B), the live test (row distance,
+    4 B) over every non-empty chunk, one read of the codes (n/4 B) and one v
+    read per reached vertex (4 B)."""
+    return (4.0 * runs["dp_cells"] + 8.0 * C * runs["dp_chunks"] + 8.0 * runs["dp_chunks"]
+            + 4.0 * C * nonempty + n_pad / 4.0 + 4.0 * np.asarray(reached, np.float64))
+
+
+def bench_dp(G, roots, torch, nonempty: int) -> dict:
     """Mean BFS time per root without and with parents: sel-max yields them from
     the product, the other semirings by the DP transformation after the BFS
-    (the paper's "No-DP" vs "DP")."""
+    (the paper's "No-DP" vs "DP"); and the roofline of the DP sweep kernel
+    (tropical distances, event-timed sweep, counted cells)."""
     out = {}
     for semi in ("tropical", "real", "boolean", "selmax"):
         row = {}
@@ -348,7 +379,36 @@ def bench_dp(G, roots, torch) -> dict:
             row["dp_ms" if dp else "no_dp_ms"] = round(tot / (2 * len(roots)), 4)
         out[semi] = row
         log(f"dp {semi}: {row}")
+    r = G.bfs(roots, "tropical", dp=True, want_parent=True, timing=True, level_cap=1)
+    torch.cuda.synchronize()
+    reached = (r.dist >= 0).sum(dim=1).cpu().numpy()
+    n_pad = (G.n + C - 1) // C * C
+    b = dp_bytes(r.runs, n_pad, nonempty, reached)
+    ms = r.runs["dp_ms"].astype(np.float64)
+    achieved = float(b.sum() / (ms.sum() * 1e-3) / 1e9)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": measured_traffic("level_kernel<dp>"),
+                       "kernel": "level_kernel<dp>", "bytes_per_launch": round(float(b.mean())),
+                       "mean_launch_ms": round(float(ms.mean()), 5),
+                       "cells_per_launch": round(float(r.runs["dp_cells"].mean()))}
+    log(f"dp roofline: {out['roofline']}")
     return out
+
+
+def batched_bytes(levels: dict, iters: int, n_pad: int, nonempty: int, pairs: int) -> float:
+    """Algorithmic bytes of one batched BFS (64-bit masks): per level the col
+    cells streamed (4 B), per processed row its visited mask read and its new
+    frontier mask written (16 B), cs + cl per processed chunk (8 B), the live
+    test (visited mask, 8 B) over every non-empty chunk, one read of the
+    gathered masks (8 B per row) and a visited-mask write per row that gained
+    bits (8 B); plus one 2-byte level record per (vertex, root) reached."""
+    cells = levels["active_cells"][:iters].astype(np.float64)
+    chunks = levels["active_chunks"][:iters].astype(np.float64)
+    disc = levels["discovered"][:iters].astype(np.float64)
+    per_level = (4.0 * cells + 16.0 * C * chunks + 8.0 * chunks + 8.0 * C * nonempty
+                 + 8.0 * n_pad + 8.0 * disc)
+    return float(per_level.sum() + 2.0 * pairs)
 
 
 def bench_batched(ss, graphgen, torch, checks: dict) -> dict:
@@ -366,6 +426,23 @@ def bench_batched(ss, graphgen, torch, checks: dict) -> dict:
     d = dist.view(64, -1)
     m_cc = float(((d >= 0).to(torch.int64) * deg[None, :]).sum() // 2)
     checks["batched_rmat_s21"] = [(e, roots, d.cpu().numpy())]
+    # roofline of the batched level kernel: per-level counters and events
+    _, it_b, lv, rs = G.bfs_batch(roots[None, :], level_cap=64, timing=True)
+    torch.cuda.synchronize()
+    pairs = int((d >= 0).sum().item()) - 64
+    deg_h = G.degrees()
+    nonempty_b = nonempty_chunks(deg_h, G.info()["chunks"])
+    n_pad_b = (G.n + C - 1) // C * C
+    bb = batched_bytes(lv, it_b, n_pad_b, nonempty_b, pairs)
+    launches = int(rs["launches"])
+    kms = float(rs["kernel_ms"])
+    achieved_b = bb / (kms * 1e-3) / 1e9
+    roof_b = {"bound": "hbm", "achieved": round(achieved_b, 1), "peak": HBM_PEAK_GBS,
+              "unit": "GB/s", "frac": round(achieved_b / HBM_PEAK_GBS, 4),
+              "traffic": measured_traffic("level_kernel<batch>"), "kernel": "level_kernel<batch>",
+              "bytes_per_launch": round(bb / launches), "mean_launch_ms": round(kms / launches, 5),
+              "levels": int(it_b), "launches": launches}
+    log(f"batched roofline: {roof_b}")
     G.bfs(roots, "selmax")
     t_plain = _events_ms(torch, lambda: G.bfs(roots, "selmax"), reps=2)
     G.bfs(roots, "boolean")
@@ -376,7 +453,7 @@ def bench_batched(ss, graphgen, torch, checks: dict) -> dict:
         "batched_ms": round(t_batch, 3), "plain_selmax_ms": round(t_plain, 3),
         "plain_boolean_ms": round(t_bool, 3), "gteps_batched": round(m_cc / t_batch / 1e6, 3),
         "gteps_plain_selmax": round(m_cc / t_plain / 1e6, 3),
-        "speedup_vs_selmax": round(t_plain / t_batch, 2)}}
+        "speedup_vs_selmax": round(t_plain / t_batch, 2), "roofline": roof_b}}
     t = time.perf_counter()
     graphs = graphgen.er_set(256, seed=3)
     Gm = ss.Graph.from_many(graphs)
@@ -491,6 +568,13 @@ def main() -> int:
                     help="skip the learned-schedule comparison (R-MAT s24, 4096^2 grid)")
     ap.add_argument("--profile-summary", action="store_true",
                     help="summarise rocprofv3 output into profiles/ (no GPU needed)")
+    ap.add_argument("--kernel", default="level_kernel<selmax>", choices=sorted(PROFILES),
+                    help="kernel --profile-summary summarises")
+    ap.add_argument("--only", choices=["batched", "dp", "push"],
+                    help="run one form alone, warm-up and timed steps only (for profiler "
+                         "runs): batched = 64 roots of R-MAT s21 in one SpMM; dp = tropical "
+                         "BFS with parents by the DP transformation, 16 roots of R-MAT s22; "
+                         "push = sel-max with the forced push schedule, 16 roots of R-MAT s22")
     for name in ("trace", "fetch", "write", "copy-fetch", "copy-write"):
         ap.add_argument("--" + name, help="rocprofv3 output directory")
         ap.add_argument("--cmd-" + name, default="", help="the command that produced it")
@@ -523,6 +607,8 @@ def main() -> int:
                           "copy_probe_bytes_written": dst.numel() * 4, "launches": 4}))
         return 0
     semi = args.semiring
+    if args.only:
+        return run_only(args, ss, graphgen, torch)
 
     t = time.perf_counter()
     e = graphgen.rmat(args.scale, 16, seed=1)
@@ -620,7 +706,7 @@ def main() -> int:
                                  "frac": round(s2.get("frac", 0.0), 4)}
             log(f"split {split}: {s2}")
         result["split_sweep"] = sweep
-        result["dp"] = bench_dp(G, roots[:16], torch)
+        result["dp"] = bench_dp(G, roots[:16], torch, nonempty)
         G.close()
         result["slimsell_vs_sell"] = bench_sell(ss, e, roots[:8], torch)
         result["storage_words"] = {"rmat_s22": storage_report(ss, e, (1, 64, 2048, 1 << 14, 0))}
@@ -650,6 +736,35 @@ def main() -> int:
     if not args.no_cpu and not args.only_timed:
         cpu_leg(args, e, roots, result, checks)
     print(json.dumps(result), flush=True)
+    return 0
+
+
+def run_only(args, ss, graphgen, torch) -> int:
+    """One form alone (warm-up, then the timed steps), for profiler runs."""
+    if args.only == "batched":
+        e = graphgen.rmat(21, 16, seed=1)
+        roots = graphgen.pick_roots(e, 64, seed=1004)
+        G = ss.Graph.from_edgelist(e, sigma=0)
+        step = lambda: G.bfs_batch(roots[None, :])  # noqa: E731
+    else:
+        e = graphgen.rmat(args.scale, 16, seed=1)
+        roots = graphgen.pick_roots(e, 16, seed=1002)
+        G = ss.Graph.from_edgelist(e, sigma=0)
+        if args.only == "dp":
+            step = lambda: G.bfs(roots, "tropical", dp=True)  # noqa: E731
+        else:
+            step = lambda: G.bfs(roots, "selmax", schedule="push")  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / max(args.steps, 1)
+    G.close()
+    print(json.dumps({"only": args.only, "steps": args.steps, "ms_per_step": round(ms, 4)}),
+          flush=True)
     return 0
 
 

@@ -249,6 +249,14 @@ typedef struct {
   int32_t launches;      /* level kernels launched, incl. look-ahead ones that exit at once */
   float kernel_ms;       /* summed time of all those level kernels (SS_STATS_TIME) */
   float bfs_ms;          /* init kernel start to finalise end on the stream (SS_STATS_TIME) */
+  /* the DP transformation's sweep kernel, when parents are asked of a
+   * semiring other than sel-max (0 otherwise): its time (SS_STATS_TIME or
+   * SS_STATS_TIME_BFS) and the chunks and col cells it swept
+   * (SS_STATS_COUNTERS with level_stats_out) */
+  float dp_ms;
+  int32_t pad0;
+  int64_t dp_chunks;
+  int64_t dp_cells;
 } ss_run_stats;
 
 #define SS_STATS_TIME 1     /* hipEvents around every level kernel and every BFS */
@@ -373,9 +381,10 @@ int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiri
  * the process ends.  The call makes no hipMalloc, hipFree or other
  * allocating call; outputs are the caller's.
  *   Scratch needed: 8 KiB + 4 B per chunk + the frontier summaries (at most
- *   32 KiB) + per row: tropical 8 B (16.25 B with parents), real 21 B,
- *   boolean 11 B, sel-max 13.25 B; more than 64 MiB is SS_EINVAL (sel-max
- *   fits about 5 million rows).
+ *   32 KiB) + per row: tropical 8 B, real 21 B, boolean 11 B, sel-max
+ *   13.25 B, and for parents by the DP transformation 4.25 B more (tropical)
+ *   or 4 B more (real, boolean); more than 64 MiB is SS_EINVAL (sel-max fits
+ *   about 5 million rows).
  *   opts   : slimwork, split_len, waves_per_group, max_levels, stream and
  *            iterations_out as slimsell_bfs; flags 0 or SS_NO_SUMMARY;
  *            schedule 0; level_stats_out and run_stats_out NULL (anything
@@ -397,10 +406,12 @@ int slimsell_bfs_noalloc(ss_graph* g, const int32_t* roots, int32_t num_roots, s
  * vertex v with dist[v] >= 1, parent[v] = the largest original ID u among
  * v's neighbours with dist[u] = dist[v] - 1 (-1 if there is none); a vertex
  * with dist 0 is its own parent; dist < 0 gives -1.  One sweep of the
- * SlimSell layout per root that gathers dist mod 3 as a 2-bit code (a
- * neighbour is one level closer, at the same level or one further, so the
- * code decides), so the input must be BFS distances on this graph (other
- * input gives unspecified parents, never an out-of-bounds access).
+ * SlimSell layout per root, by the level kernel with the reached rows live,
+ * that gathers dist mod 3 as a 2-bit code (a neighbour is one level closer,
+ * at the same level or one further, so the code decides); a row stops at its
+ * first qualifying neighbour, the largest.  The input must be BFS distances
+ * on this graph (other input gives unspecified parents, never an
+ * out-of-bounds access).
  *   dist      : device int32[num_roots * n], original vertex order (as
  *               slimsell_bfs or slimsell_bfs_batch write it).
  *   parent    : device int32[num_roots * n], written.

@@ -98,7 +98,8 @@ _LEVEL_DTYPE = np.dtype([("discovered", "<i8"), ("frontier_edges", "<i8"),
                          ("active_chunks", "<i8"), ("active_cells", "<i8"),
                          ("max_active_cl", "<i8"), ("ms", "<f4"), ("variant", "<i4")])
 _RUN_DTYPE = np.dtype([("iterations", "<i4"), ("launches", "<i4"), ("kernel_ms", "<f4"),
-                       ("bfs_ms", "<f4")])
+                       ("bfs_ms", "<f4"), ("dp_ms", "<f4"), ("pad0", "<i4"),
+                       ("dp_chunks", "<i8"), ("dp_cells", "<i8")])
 
 
 def _records(buf, dtype, shape):
@@ -108,7 +109,7 @@ def _records(buf, dtype, shape):
 VARIANTS = ("pull", "pull-split256", "pull-split1024", "push")
 SCHEDULES = {"none": 0, "learned": 1, "heuristic": 2, "pull": 3, "pull-split256": 4,
              "pull-split1024": 5, "push": 6}
-RUN_FIELDS = ("iterations", "launches", "kernel_ms", "bfs_ms")
+RUN_FIELDS = ("iterations", "launches", "kernel_ms", "bfs_ms", "dp_ms", "dp_chunks", "dp_cells")
 
 
 @dataclass

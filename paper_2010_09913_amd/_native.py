@@ -55,6 +55,8 @@ class RunStats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
         ("kernel_ms", ctypes.c_float), ("bfs_ms", ctypes.c_float),
+        ("dp_ms", ctypes.c_float), ("pad0", ctypes.c_int32),
+        ("dp_chunks", ctypes.c_int64), ("dp_cells", ctypes.c_int64),
     ]
 
 

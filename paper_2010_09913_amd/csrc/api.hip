@@ -304,9 +304,14 @@ struct RunPlan {
 
 // Per-call record of what was launched, for the statistics epilogue.
 struct RunLog {
-  explicit RunLog(size_t runs) : ev_first(runs, 0), launches(runs, 0), iters(runs, 0) {}
+  explicit RunLog(size_t runs)
+      : ev_first(runs, 0), ev_last(runs, 0), ev_dp(runs, 0), dp(runs, 0), launches(runs, 0),
+        iters(runs, 0) {}
   size_t next_ev = 0;
-  std::vector<size_t> ev_first;
+  std::vector<size_t> ev_first;  // event before the run's first kernel
+  std::vector<size_t> ev_last;   // event after its last kernel
+  std::vector<size_t> ev_dp;     // first of the two events around its DP sweep (timing)
+  std::vector<char> dp;          // whether the run ended with the DP transformation
   std::vector<int32_t> launches;
   std::vector<int32_t> iters;
 };
@@ -414,7 +419,8 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   p->level_events = (o->flags & SS_STATS_TIME) && !(o->flags & SS_STATS_TIME_BFS);
   p->lcap = o->level_cap;
   p->counting = (o->flags & SS_STATS_COUNTERS) && p->lcap > 0 && o->level_stats_out;
-  p->words_per_run = (p->lcap + 1) * kCountSlots * kCountFields;
+  // levels 0..lcap, then one block for the DP transformation's sweep
+  p->words_per_run = (p->lcap + 2) * kCountSlots * kCountFields;
   if (p->counting) {
     rc = ensure_counters(g, p->words_per_run * runs);
     if (rc) return rc;
@@ -649,26 +655,39 @@ static int collect_stats(Graph& g, const ss_bfs_opts* o, const RunPlan& p, int32
   for (int32_t r = 0; r < runs; ++r) {
     float kernel_ms = 0.f, bfs_ms = 0.f;
     std::vector<float> lvl_ms((size_t)log.launches[r], 0.f);
-    if (p.timing && !p.level_events) {
+    float dp_ms = 0.f;
+    if (p.timing) {
       const size_t e = log.ev_first[r];
-      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1)));
-    } else if (p.timing) {
-      const size_t e = log.ev_first[r];
-      for (int32_t k = 0; k < log.launches[r]; ++k) {
-        float ms = 0.f;
-        SS_HIP(hipEventElapsedTime(&ms, ev(e + 1 + 2 * k), ev(e + 2 + 2 * k)));
-        lvl_ms[k] = ms;
-        kernel_ms += ms;
+      if (p.level_events) {
+        for (int32_t k = 0; k < log.launches[r]; ++k) {
+          float ms = 0.f;
+          SS_HIP(hipEventElapsedTime(&ms, ev(e + 1 + 2 * k), ev(e + 2 + 2 * k)));
+          lvl_ms[k] = ms;
+          kernel_ms += ms;
+        }
+        if (p.persistent) std::fill(lvl_ms.begin(), lvl_ms.end(), 0.f);  // one launch, all levels
       }
-      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(e + 1 + 2 * log.launches[r])));
-      if (p.persistent) std::fill(lvl_ms.begin(), lvl_ms.end(), 0.f);  // one launch, all levels
+      SS_HIP(hipEventElapsedTime(&bfs_ms, ev(e), ev(log.ev_last[r])));
+      if (log.dp[r])
+        SS_HIP(hipEventElapsedTime(&dp_ms, ev(log.ev_dp[r]), ev(log.ev_dp[r] + 1)));
     }
     if (o->run_stats_out) {
       ss_run_stats& rs = o->run_stats_out[r];
+      std::memset(&rs, 0, sizeof(rs));
       rs.iterations = log.iters[r];
       rs.launches = log.launches[r];
       rs.kernel_ms = kernel_ms;
       rs.bfs_ms = bfs_ms;
+      rs.dp_ms = dp_ms;
+      if (p.counting && log.dp[r]) {
+        // the DP sweep's block sits behind the levels (see words_per_run)
+        const unsigned long long* base =
+            h.data() + p.words_per_run * r + (p.lcap + 1) * kCountSlots * kCountFields;
+        for (int q = 0; q < kCountSlots; ++q) {
+          rs.dp_chunks += (int64_t)base[q * kCountFields + 1];
+          rs.dp_cells += (int64_t)base[q * kCountFields + 2];
+        }
+      }
     }
     if (want_levels) {
       for (int64_t k = 1; k <= p.lcap; ++k) {
@@ -815,6 +834,7 @@ static int64_t carve_workspace(const Graph& g, int semiring, bool dp, uint8_t* b
     w->d = static_cast<int32_t*>(take(4 * n));
     w->g = static_cast<uint8_t*>(take(n / 4));
   }
+  if (dp && !w->state) w->state = static_cast<int32_t*>(take(4 * n));  // best v per row
   // the graph's host-mapped report ring (part of the graph, not scratch)
   w->h_report = g.ws.h_report;
   w->d_report = g.ws.d_report;
@@ -1087,11 +1107,24 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
     // the other semirings get parents by the DP transformation (Section II-C)
-    if (parent_r && s != SS_SELMAX &&
-        (rc = launch_dp(g, g.ws, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
-                        parent_r, st)))
-      return rc;
-    if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
+    if (parent_r && s != SS_SELMAX) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      log.dp[r] = 1;
+      if (plan.timing) {
+        log.ev_dp[r] = log.next_ev;
+        if ((rc = pool_event(g, log.next_ev++, &e0))) return rc;
+        if ((rc = pool_event(g, log.next_ev++, &e1))) return rc;
+      }
+      // its counters go to the block behind the run's levels, addressed as
+      // level 1 by the sweep
+      unsigned long long* dpc =
+          plan.counting ? g.ws.counters + plan.words_per_run * r + plan.lcap * kCountSlots * kCountFields
+                        : nullptr;
+      if ((rc = launch_dp(g, g.ws, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
+                          parent_r, st, dpc, e0, e1)))
+        return rc;
+    }
+    if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_last[r]))) return rc;
   }
   return collect_stats(g, o, plan, num_roots, log, st);
 }
@@ -1171,7 +1204,7 @@ int slimsell_bfs_batch(ss_graph* gp, const int32_t* roots, int32_t rpg, const ss
   if (o->iterations_out) o->iterations_out[0] = log.iters[0];
   rc = launch_batch_finalise(g, bw, rpg, dist, st);
   if (rc) return rc;
-  if ((rc = mark_event(g, plan, log.next_ev, st, nullptr))) return rc;
+  if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_last[0]))) return rc;
   return collect_stats(g, o, plan, 1, log, st);
 }
 

@@ -70,7 +70,8 @@ __device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint3
 // The product terms of one block of U columns: element c[t] of the gathered
 // vector for each lane (c[t] = -1 is padding).  KIND 0: one byte per row;
 // 1: four bytes per row; 2: the 32-bit word of a one-bit-per-row bitmap that
-// holds row c.  A term is read from LDS when the staged prefix holds it.
+// holds row c; 3: the byte of a two-bits-per-row code that holds row c.  A
+// term is read from LDS when the staged prefix holds it.
 // With the filter on, a term outside the prefix is read from memory only
 // when its row's chunk had a row enter the frontier in the previous level;
 // otherwise it is left unread (got[t] false, y[t] 0).  If no lane of the
@@ -82,8 +83,11 @@ __device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint3
 template <int KIND>
 __device__ __forceinline__ uint32_t row_offset(int32_t c) {  // byte offset of row c's element
   const uint32_t cu = (uint32_t)c;
-  return c < 0 ? kOob : KIND == 0 ? cu : KIND == 1 ? (cu << 2) : ((cu >> 5) << 2);
+  return c < 0 ? kOob
+               : KIND == 0 ? cu : KIND == 1 ? (cu << 2) : KIND == 2 ? ((cu >> 5) << 2) : (cu >> 2);
 }
+template <int KIND>
+constexpr bool byte_kind() { return KIND == 0 || KIND == 3; }  // elements read one byte at a time
 template <int U, bool STAGED, int KIND>
 __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)[U],
                                             uint32_t (&y)[U], bool (&got)[U]) {
@@ -98,11 +102,11 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
       uint32_t l = 0u;
       if (STAGED) {
         const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : 0u));
-        l = !in ? 0u : KIND == 0 ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
+        l = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
       }
       const uint32_t o = in ? kOob : off;
-      y[t] = l | (KIND == 0 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o, 0, 0)
-                            : __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+      y[t] = l | (byte_kind<KIND>() ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o, 0, 0)
+                                    : __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
       got[t] = c[t] >= 0;
     }
     return;
@@ -119,7 +123,7 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     // else the summary word of its chunk (stored right behind the prefix)
     const uint32_t sw = st.bytes + ((cu >> 11) << 2);
     const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
-    y[t] = !in ? 0u : KIND == 0 ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
+    y[t] = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
     const uint32_t need = (valid && !in ? 1u : 0u) & (v >> ((cu >> 6) & 31u));
     o[t] = need ? off : kOob;
     some = some || need;
@@ -130,8 +134,8 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
   if (__any(some)) {
 #pragma unroll
     for (int t = 0; t < U; ++t)
-      g[t] = KIND == 0 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o[t], 0, 0)
-                       : __builtin_amdgcn_raw_buffer_load_b32(r, o[t], 0, 0);
+      g[t] = byte_kind<KIND>() ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o[t], 0, 0)
+                               : __builtin_amdgcn_raw_buffer_load_b32(r, o[t], 0, 0);
   }
 #pragma unroll
   for (int t = 0; t < U; ++t) {

@@ -104,6 +104,7 @@ struct Workspace {
 };
 
 constexpr int kBatchSemiring = 4;  // level-kernel policy id of the batched SpMM
+constexpr int kDpSemiring = 5;     // level-kernel policy id of the DP transformation's sweep
 
 // Device workspace of the batched SpMM (allocated on first use).
 struct BatchWorkspace {
@@ -279,9 +280,15 @@ int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
                        const LevelArgs& a, const SchedLaunch& p, void* stream);
 // DP transformation (dp.hip): parents (original IDs) from distances (original
 // IDs) of one root, through the workspace's d (4 B per row), g (n_pad / 4
-// bytes of codes) and acc (4 B per row) buffers.
+// bytes of codes), acc and state (4 B per row each) and arrive buffers.
+// `state` receives each row's best v.  With `counters` (one level's
+// counter block, see LevelArgs::counters, written at level index 1) the sweep
+// counts its chunks and cells; ev_begin/ev_end (hipEvent_t or NULL) bracket
+// the sweep kernel.
 int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unroll, int waves,
-              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream);
+              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream,
+              unsigned long long* counters = nullptr, void* ev_begin = nullptr,
+              void* ev_end = nullptr);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
 int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_row, bool summary,
                 void* stream);

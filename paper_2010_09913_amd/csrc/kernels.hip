@@ -51,6 +51,8 @@ struct Tropical {
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
+  // per-lane value the product terms of a row depend on (none here)
+  __device__ static uint32_t context(const LevelArgs&, int32_t) { return 0u; }
   __device__ static bool settled(Acc acc) { return acc != kInf; }
   __device__ static Acc identity() { return kInf; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
@@ -59,7 +61,7 @@ struct Tropical {
   __device__ static const void* staged(const LevelArgs& a) { return a.state; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, uint32_t) {
     uint32_t y[U];
     bool got[U];
     gather_rows<U, STAGED, 1>(r, st, c, y, got);
@@ -103,6 +105,8 @@ struct Real {
   using Acc = float;
   // a row's value is known only after all its terms (a sum of frontier terms)
   static constexpr bool kFirstHitFinal = false;
+  // per-lane value the product terms of a row depend on (none here)
+  __device__ static uint32_t context(const LevelArgs&, int32_t) { return 0u; }
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0.0f; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
@@ -110,7 +114,7 @@ struct Real {
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, uint32_t) {
     uint32_t y[U];
     bool got[U];
     gather_rows<U, STAGED, 1>(r, st, c, y, got);  // unread terms are 0.0f
@@ -151,6 +155,8 @@ struct Boolean {
   using Acc = uint32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
+  // per-lane value the product terms of a row depend on (none here)
+  __device__ static uint32_t context(const LevelArgs&, int32_t) { return 0u; }
   __device__ static bool settled(Acc acc) { return acc != 0u; }
   __device__ static Acc identity() { return 0u; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
@@ -158,7 +164,7 @@ struct Boolean {
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, uint32_t) {
     uint32_t y[U];
     bool got[U];
     gather_rows<U, STAGED, 0>(r, st, c, y, got);  // unread terms are 0
@@ -205,6 +211,8 @@ struct SelMax {
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
+  // per-lane value the product terms of a row depend on (none here)
+  __device__ static uint32_t context(const LevelArgs&, int32_t) { return 0u; }
   __device__ static bool settled(Acc acc) { return acc != 0; }
   __device__ static Acc identity() { return 0; }
   __device__ static Rsrc rsrc(const LevelArgs& a) {
@@ -214,7 +222,7 @@ struct SelMax {
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, uint32_t) {
     const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
     uint32_t w[U];  // the 32-bit half of the chunk word holding bit c (0 if unread)
     bool got[U];
@@ -276,6 +284,8 @@ struct Batch {
   using Acc = unsigned long long;
   // a row's masks are known only after all its terms (an OR over neighbours)
   static constexpr bool kFirstHitFinal = false;
+  // per-lane value the product terms of a row depend on (none here)
+  __device__ static uint32_t context(const LevelArgs&, int32_t) { return 0u; }
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0ull; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 8u); }
@@ -286,7 +296,7 @@ struct Batch {
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
-                              Acc acc) {
+                              Acc acc, uint32_t) {
     Acc y[U];
     gather_masks<U, STAGED>(r, st, c, y);  // unread masks are 0
 #pragma unroll
@@ -312,6 +322,66 @@ struct Batch {
   __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
 };
 
+// DP transformation (Section II-C) as one more pass of the level kernel:
+// the parent of a reached row other than the root is its largest-ID
+// neighbour one level closer.  The gathered vector is a code of two bits per
+// row, distance mod 3 (3 = unreached), four rows per byte: a neighbour of a
+// row at level k sits at level k-1, k or k+1, so the code tells the closer
+// ones apart, and the gathered array is n/4 bytes.  A hit reads v of the
+// neighbour (original ID + 1) and the max keeps the largest; rows list their
+// neighbours by decreasing original ID, so a row stops at its first hit, as
+// under sel-max.  The live rows are the reached ones other than the root (d
+// holds row distances); each row's best v goes to `state`.
+struct Dp {
+  static constexpr bool kSingleRoot = true;
+  using Acc = int32_t;
+  // the first hit is the largest qualifying ID
+  static constexpr bool kFirstHitFinal = true;
+  // the code a qualifying neighbour of this lane's row carries (4: none)
+  __device__ static uint32_t context(const LevelArgs& a, int32_t row) {
+    const int32_t d = a.d[row];
+    return d >= 1 ? (uint32_t)((d - 1) % 3) : 4u;
+  }
+  __device__ static bool settled(Acc acc) { return acc != 0; }
+  __device__ static Acc identity() { return 0; }
+  __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad / 4u); }
+  __device__ static bool live(const LevelArgs& a, int32_t row) { return a.d[row] >= 1; }
+  __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
+  template <int U, bool STAGED>
+  __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
+                              Acc acc, uint32_t want) {
+    const Rsrc rv = make_rsrc(a.v, a.n_pad * 4u);
+    uint32_t y[U];  // the code byte holding row c (0 if unread)
+    bool got[U];
+    gather_rows<U, STAGED, 3>(r, st, c, y, got);
+    bool hit[U];
+    bool some = false;
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      hit[t] = c[t] >= 0 && ((y[t] >> ((c[t] & 3) * 2)) & 3u) == want;
+      some = some || hit[t];
+    }
+    if (__any(some)) {
+      int32_t x[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t)
+        x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit[t] ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+#pragma unroll
+      for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
+    }
+    return acc;
+  }
+  __device__ static void atomic_combine(const LevelArgs& a, int32_t row, Acc v) {
+    keep(atomicMax(&a.acc[row], v));
+  }
+  __device__ static Acc take(const LevelArgs& a, int32_t row) { return atomicExch(&a.acc[row], 0); }
+  __device__ static bool post(const LevelArgs& a, int32_t row, Acc acc, bool) {
+    a.state[row] = acc;
+    return false;
+  }
+  __device__ static void publish(const LevelArgs&, int32_t, uint64_t, int) {}
+};
+
 // ---------------------------------------------------------- level kernel ---
 
 
@@ -330,7 +400,7 @@ struct Batch {
 template <class S, int U, bool STAGED, bool VAL = false>
 __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Stage st,
                                                  const int32_t* __restrict__ p, int32_t ncols,
-                                                 bool on, int32_t& cols) {
+                                                 bool on, uint32_t ctx, int32_t& cols) {
   typename S::Acc acc = S::identity();
   cols = 0;
   if (!on) return acc;
@@ -361,7 +431,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, ctx);
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
         go = false;
         break;
@@ -379,7 +449,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
 #pragma unroll
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, ctx);
       go = !(S::kFirstHitFinal && stop && S::settled(acc));
       cols = j;
     } else {
@@ -399,7 +469,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
         for (int t = 0; t < U; ++t) c[t] = w[t] ? c[t] : -1;
         pv += (int64_t)U * kC;
       }
-      acc = S::template block<U, STAGED>(a, r, st, c, acc);
+      acc = S::template block<U, STAGED>(a, r, st, c, acc, ctx);
       p += (int64_t)U * kC;
       cols = j + U;
       if (S::kFirstHitFinal && stop && S::settled(acc)) {
@@ -422,7 +492,7 @@ __device__ __forceinline__ typename S::Acc sweep(const LevelArgs& a, Rsrc r, Sta
     }
 #pragma unroll
     for (int t = 0; t < U; ++t) c[t] = t < rem ? c[t] : -1;
-    acc = S::template block<U, STAGED>(a, r, st, c, acc);
+    acc = S::template block<U, STAGED>(a, r, st, c, acc, ctx);
     cols = ncols;
   }
   return acc;
@@ -602,7 +672,8 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       const int32_t ncols = hi > j0 ? hi - j0 : 0;
       const int32_t* p = a.col + start + (int64_t)j0 * kC + lane;
       int32_t lane_cols;
-      typename S::Acc acc = sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on, lane_cols);
+      typename S::Acc acc =
+          sweep<S, U, STAGED, VAL>(a, rs, st, p, ncols, on, S::context(a, row), lane_cols);
       n_cols += (uint64_t)wave_max(lane_cols);  // columns the wavefront streamed
       const int32_t npieces = piece ? pieces[c] : 1;
       if (npieces == 1) {
@@ -630,10 +701,8 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
 }
 
 
-template <class S, int U, bool STAGED, bool VAL = false>
-__global__ void level_kernel(LevelArgs a) {
-  extern __shared__ uint8_t lds_stage[];
-
+template <class S, int U, bool STAGED, bool VAL>
+__device__ __forceinline__ void level_entry(const LevelArgs& a, uint8_t* lds_stage) {
   if (a.level > 1) {
     // Stop if the previous level discovered nothing, and tell the host what
     // the previous level found (one thread of the first workgroup).
@@ -645,8 +714,23 @@ __global__ void level_kernel(LevelArgs a) {
     }
     if (!prev_found) return;
   }
-
   level_body<S, U, STAGED, VAL>(a, a.units, a.pieces, a.n_units, lds_stage);
+}
+
+template <class S, int U, bool STAGED, bool VAL = false>
+__global__ void level_kernel(LevelArgs a) {
+  extern __shared__ uint8_t lds_stage[];
+  level_entry<S, U, STAGED, VAL>(a, lds_stage);
+}
+
+// The four-column form held to 64 registers per lane, so that eight
+// wavefronts share each SIMD: two 16-wavefront workgroups per compute unit,
+// twice the wavefronts of the eight-column form, for levels that are bound
+// by the latency of their per-chunk loads rather than by the column stream.
+template <class S, bool STAGED>
+__global__ void __launch_bounds__(1024, 8) level_kernel_w8(LevelArgs a) {
+  extern __shared__ uint8_t lds_stage[];
+  level_entry<S, 4, STAGED, false>(a, lds_stage);
 }
 
 // ------------------------------------------------------- persistent form ---
@@ -1338,8 +1422,12 @@ static void launch_level_u(int waves, int unroll, unsigned grid, const LevelArgs
   const size_t lds = STAGED ? level_lds(a) : 0;
   if (a.val)  // the Sell-C-sigma comparator is built for one unroll depth
     level_kernel<S, 8, STAGED, true><<<grid, waves * kC, lds, st>>>(a);
-  else if (unroll == 4)
-    level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a);
+  else if (unroll == 4) {
+    if constexpr (S::kSingleRoot)
+      level_kernel_w8<S, STAGED><<<grid, waves * kC, lds, st>>>(a);
+    else
+      level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a);
+  }
   else if (unroll == 16)
     level_kernel<S, 16, STAGED><<<grid, waves * kC, lds, st>>>(a);
   else
@@ -1368,6 +1456,7 @@ int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const 
     case SS_BOOLEAN: launch_level_t<Boolean>(waves, unroll, grid, a, st); break;
     case SS_SELMAX: launch_level_t<SelMax>(waves, unroll, grid, a, st); break;
     case kBatchSemiring: launch_level_t<Batch>(waves, unroll, grid, a, st); break;
+    case kDpSemiring: launch_level_t<Dp>(waves, unroll, grid, a, st); break;
     default: return set_error(SS_EINVAL, "unknown semiring");
   }
   return check_launch("level_kernel");
