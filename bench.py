@@ -33,7 +33,6 @@ C = 64
 # Bytes each processed row moves in the level post-processing and the
 # gathered-vector element size (see the byte model in the design notes).
 ROW_BYTES = {"tropical": 8, "real": 14, "boolean": 7, "selmax": 16}
-TEST_BYTES = {"tropical": 4, "real": 1, "boolean": 1, "selmax": 4}
 GATHER_BYTES = {"tropical": 4, "real": 4, "boolean": 1, "selmax": 4}
 
 
@@ -178,13 +177,33 @@ def nonempty_chunks(deg: np.ndarray, chunks: int) -> int:
     return int((np.count_nonzero(deg) + C - 1) // C)
 
 
+def work_units(deg: np.ndarray, split: int) -> int:
+    """Work units of a level under a full sort (chunk lengths are the
+    degrees of every 64th row in decreasing order) for SlimChunk split
+    length `split`, without packing: one per non-empty chunk, or one per
+    piece of a chunk longer than `split`."""
+    d = np.sort(np.asarray(deg, np.int64))[::-1]
+    cl = d[::C]
+    cl = cl[cl > 0]
+    if split <= 0:
+        return int(len(cl))
+    return int(np.where(cl > split, (cl + split - 1) // split, 1).sum())
+
+
+# Bytes a level reads per work unit besides its chunk: the 16-byte unit
+# descriptor and the chunk's one-byte "all rows final" flag (a unit whose
+# chunk is final is skipped after these; the rows of every processed chunk
+# are counted in ROW_BYTES).
+UNIT_BYTES = 17
+
+
 def algorithmic_bytes(levels: dict, r: int, iters: int, semi: str, n: int,
-                      nonempty_chunks: int) -> float:
+                      units: int) -> float:
     """Bytes the method must move for all levels of root r."""
     cells = levels["active_cells"][r][:iters].astype(np.float64)
     chunks = levels["active_chunks"][r][:iters].astype(np.float64)
     per_level = (4.0 * cells + ROW_BYTES[semi] * C * chunks + 8.0 * chunks
-                 + TEST_BYTES[semi] * C * nonempty_chunks + GATHER_BYTES[semi] * n)
+                 + UNIT_BYTES * units + GATHER_BYTES[semi] * n)
     return float(per_level.sum())
 
 
@@ -227,7 +246,7 @@ def run_workload(ss, G, roots, semi, split, steps, warmup, deg_t, count_pass=Tru
     return out
 
 
-def summarise(out, roots, semi, n, nonempty_chunks, steps):
+def summarise(out, roots, semi, n, units, steps):
     m_cc = out["m_cc"].astype(np.float64)
     bfs_ms = np.stack([r["bfs_ms"] for r in out["runs"]])        # [steps, roots]
     kern_ms = out["kernel_runs"]["kernel_ms"]                      # [roots], one step
@@ -240,8 +259,8 @@ def summarise(out, roots, semi, n, nonempty_chunks, steps):
              mean_launch_ms=float(kern_ms.sum() / launches.sum()))
     if "levels" in out:
         iters = out["iterations"]
-        per_root = np.array([algorithmic_bytes(out["levels"], i, int(iters[i]), semi, n,
-                                               nonempty_chunks) for i in range(len(roots))])
+        per_root = np.array([algorithmic_bytes(out["levels"], i, int(iters[i]), semi, n, units)
+                             for i in range(len(roots))])
         bytes_per_step = per_root.sum()
         kernel_s = kern_ms.sum() / 1e3
         achieved = bytes_per_step / kernel_s / 1e9
@@ -396,17 +415,17 @@ def bench_dp(G, roots, torch, nonempty: int) -> dict:
     return out
 
 
-def batched_bytes(levels: dict, iters: int, n_pad: int, nonempty: int, pairs: int) -> float:
+def batched_bytes(levels: dict, iters: int, n_pad: int, units: int, pairs: int) -> float:
     """Algorithmic bytes of one batched BFS (64-bit masks): per level the col
     cells streamed (4 B), per processed row its visited mask read and its new
-    frontier mask written (16 B), cs + cl per processed chunk (8 B), the live
-    test (visited mask, 8 B) over every non-empty chunk, one read of the
-    gathered masks (8 B per row) and a visited-mask write per row that gained
-    bits (8 B); plus one 2-byte level record per (vertex, root) reached."""
+    frontier mask written (16 B), cs + cl per processed chunk (8 B), each work
+    unit's descriptor and chunk flag (UNIT_BYTES), one read of the gathered
+    masks (8 B per row) and a visited-mask write per row that gained bits
+    (8 B); plus one 2-byte level record per (vertex, root) reached."""
     cells = levels["active_cells"][:iters].astype(np.float64)
     chunks = levels["active_chunks"][:iters].astype(np.float64)
     disc = levels["discovered"][:iters].astype(np.float64)
-    per_level = (4.0 * cells + 16.0 * C * chunks + 8.0 * chunks + 8.0 * C * nonempty
+    per_level = (4.0 * cells + 16.0 * C * chunks + 8.0 * chunks + UNIT_BYTES * units
                  + 8.0 * n_pad + 8.0 * disc)
     return float(per_level.sum() + 2.0 * pairs)
 
@@ -431,9 +450,9 @@ def bench_batched(ss, graphgen, torch, checks: dict) -> dict:
     torch.cuda.synchronize()
     pairs = int((d >= 0).sum().item()) - 64
     deg_h = G.degrees()
-    nonempty_b = nonempty_chunks(deg_h, G.info()["chunks"])
+    units_b = work_units(deg_h, G.get_tune()["split_len"])
     n_pad_b = (G.n + C - 1) // C * C
-    bb = batched_bytes(lv, it_b, n_pad_b, nonempty_b, pairs)
+    bb = batched_bytes(lv, it_b, n_pad_b, units_b, pairs)
     launches = int(rs["launches"])
     kms = float(rs["kernel_ms"])
     achieved_b = bb / (kms * 1e-3) / 1e9
@@ -623,9 +642,12 @@ def main() -> int:
     log(f"built SlimSell layout in {build_s:.1f}s: {info}")
     nonempty = nonempty_chunks(deg, info["chunks"])
 
+    def units_of(split):
+        return work_units(deg, G.get_tune()["split_len"] if split == -1 else split)
+
     out = run_workload(ss, G, roots, semi, args.split, args.steps, args.warmup, deg_t,
                        count_pass=not args.only_timed)
-    s = summarise(out, roots, semi, e.n, nonempty, args.steps)
+    s = summarise(out, roots, semi, e.n, units_of(args.split), args.steps)
     log(f"main: {s}")
 
     result = {
@@ -677,7 +699,7 @@ def main() -> int:
                 ss.sched_load(np.load(scheduler.DEFAULT_MODEL))
             o2 = run_workload(ss, G, roots, semi, args.split, max(1, args.steps // 2), 1, deg_t,
                               count_pass=False, schedule=sched, persistent=pers)
-            s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+            s2 = summarise(o2, roots, semi, e.n, units_of(args.split), max(1, args.steps // 2))
             name = ("pull" if sched == "none" else sched + "_schedule") + (
                 "_persistent" if pers else "")
             forms[name] = {"gteps": round(s2["gteps_wall"], 4),
@@ -691,7 +713,7 @@ def main() -> int:
         at = G.autotune(roots[:8], semi, repeats=2, force=True)
         tune_s = time.perf_counter() - t
         o2 = run_workload(ss, G, roots, semi, -1, max(1, args.steps // 2), 1, deg_t)
-        s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+        s2 = summarise(o2, roots, semi, e.n, units_of(-1), max(1, args.steps // 2))
         forms["autotuned"] = {"gteps": round(s2["gteps_wall"], 4),
                               "frac": round(s2.get("frac", 0.0), 4), "tune": at["best"],
                               "configs_timed": at["evaluated"], "tune_s": round(tune_s, 1)}
@@ -701,7 +723,7 @@ def main() -> int:
         sweep = {}
         for split in (0, 256, 1024, 4096):
             o2 = run_workload(ss, G, roots, semi, split, max(1, args.steps // 2), 1, deg_t)
-            s2 = summarise(o2, roots, semi, e.n, nonempty, max(1, args.steps // 2))
+            s2 = summarise(o2, roots, semi, e.n, units_of(split), max(1, args.steps // 2))
             sweep[str(split)] = {"gteps": round(s2["gteps_wall"], 4),
                                  "frac": round(s2.get("frac", 0.0), 4)}
             log(f"split {split}: {s2}")
@@ -715,7 +737,8 @@ def main() -> int:
         er_roots = graphgen.pick_roots(er, args.roots, seed=1003)
         Ge = ss.Graph.from_edgelist(er, sigma=0)
         deg_e = torch.from_numpy(Ge.degrees().astype(np.int64)).cuda()
-        ne = nonempty_chunks(Ge.degrees(), Ge.info()["chunks"])
+        sp = Ge.get_tune()["split_len"] if args.split == -1 else args.split
+        ne = work_units(Ge.degrees(), sp)
         oe = run_workload(ss, Ge, er_roots, semi, args.split, max(1, args.steps // 2), 1, deg_e)
         se = summarise(oe, er_roots, semi, er.n, ne, max(1, args.steps // 2))
         log(f"er: {se}")

@@ -380,7 +380,7 @@ int slimsell_bfs(ss_graph* g, const int32_t* roots, int32_t num_roots, ss_semiri
  * 64 MiB device array that the library holds on every GPU it runs on until
  * the process ends.  The call makes no hipMalloc, hipFree or other
  * allocating call; outputs are the caller's.
- *   Scratch needed: 8 KiB + 4 B per chunk + the frontier summaries (at most
+ *   Scratch needed: 8 KiB + 5 B per chunk + the frontier summaries (at most
  *   32 KiB) + per row: tropical 8 B, real 21 B, boolean 11 B, sel-max
  *   13.25 B, and for parents by the DP transformation 4.25 B more (tropical)
  *   or 4 B more (real, boolean); more than 64 MiB is SS_EINVAL (sel-max fits

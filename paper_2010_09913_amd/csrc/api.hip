@@ -78,7 +78,7 @@ static void release_graph(Graph* g) {
   void* ptrs[] = {g->d_col,     g->d_cs,   g->d_cl,    g->d_v,     g->d_perm, g->d_deg,
                   g->d_scol,    g->d_sval,
                   g->ws.vec_a,  g->ws.vec_b, g->ws.state, g->ws.g, g->ws.d,
-                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.any, g->ws.counters,
+                  g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.done, g->ws.any, g->ws.counters,
                   g->d_voff,    g->bw.vis, g->bw.fa,   g->bw.fb,   g->bw.acc64,
                   g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots,
                   g->ws.q[0],   g->ws.q[1], g->ws.qn,   g->ws.variant, g->ws.ring_ctr,
@@ -144,6 +144,17 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
       ++i;
     }
   }
+  // Longest units first: a level hands units to its wavefronts round-robin,
+  // so this order spreads the long ones evenly over the grid (the greedy
+  // longest-first rule) and leaves the short ones to fill in.
+  auto cost = [&](const Unit& w) -> int64_t {
+    if (w.c1 == w.c0 + 1) return (int64_t)w.j1 - w.j0;
+    int64_t cols = 0;
+    for (int32_t c = w.c0; c < w.c1; ++c) cols += g.h_cl[c];
+    return cols;
+  };
+  std::stable_sort(units.begin(), units.end(),
+                   [&](const Unit& x, const Unit& y) { return cost(x) > cost(y); });
   UnitList ul;
   ul.split_len = split;
   ul.pack_cols = pack;
@@ -203,6 +214,7 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.acc, g.n_pad))) return rc;
   if ((rc = dalloc(&ws.arrive, g.n_chunks))) return rc;
   SS_HIP(hipMemset(ws.arrive, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.n_chunks)));
+  if ((rc = dalloc(&ws.done, g.n_chunks))) return rc;
   if ((rc = dalloc(&ws.q[0], g.n_pad))) return rc;
   if ((rc = dalloc(&ws.q[1], g.n_pad))) return rc;
   if ((rc = dalloc(&ws.qn, kRing))) return rc;
@@ -460,6 +472,7 @@ static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, cons
   a.rv = ws.rv;
   a.acc = ws.acc;
   a.arrive = ws.arrive;
+  a.done = ws.done;
   a.any = ws.any;
   a.counters = p.counting ? g.ws.counters + p.words_per_run * run_idx : nullptr;
   a.report = g.ws.d_report;
@@ -798,6 +811,7 @@ static int64_t carve_workspace(const Graph& g, int semiring, bool dp, uint8_t* b
   w->n_pad = n;
   w->any = static_cast<uint64_t*>(take(8 * (int64_t)kRing));
   w->arrive = static_cast<int32_t*>(take(4 * nc));
+  w->done = static_cast<uint8_t*>(take(nc));
   if (g.ws.summ) {
     w->summ = static_cast<uint32_t*>(take(4 * (3 * (int64_t)g.ws.summ_words + 4)));
     w->summ_words = g.ws.summ_words;

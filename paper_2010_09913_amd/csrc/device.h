@@ -33,9 +33,10 @@ __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)
 struct Stage {
   const uint8_t* lds;
   uint32_t bytes;  // 0 = nothing staged
-  // filter: the frontier summary sits in LDS right behind the prefix (at
-  // byte `bytes`), one bit per 64-row chunk, and this level uses it
+  // filter: the frontier summary sits in LDS at byte `summ` (right behind
+  // the largest prefix), one bit per 64-row chunk, and this level uses it
   bool filter = false;
+  uint32_t summ = 0;
 };
 
 template <bool STAGED>
@@ -120,8 +121,8 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     const uint32_t off = row_offset<KIND>(c[t]);
     const bool in = off < st.bytes;
     // one LDS read per term: the staged element if the prefix holds it,
-    // else the summary word of its chunk (stored right behind the prefix)
-    const uint32_t sw = st.bytes + ((cu >> 11) << 2);
+    // else the summary word of its chunk
+    const uint32_t sw = st.summ + ((cu >> 11) << 2);
     const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
     y[t] = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
     const uint32_t need = (valid && !in ? 1u : 0u) & (v >> ((cu >> 6) & 31u));
@@ -164,7 +165,7 @@ __device__ __forceinline__ void gather_masks(Rsrc r, Stage st, const int32_t (&c
     const uint32_t off = valid ? cu << 3 : kOob;
     const bool in = off < st.bytes;
     // the staged mask, or (as its low word) the summary word of the chunk
-    const uint32_t sw = st.bytes + ((cu >> 11) << 2);
+    const uint32_t sw = st.summ + ((cu >> 11) << 2);
     unsigned long long v;
     if (in) {
       v = *reinterpret_cast<const unsigned long long*>(st.lds + off);

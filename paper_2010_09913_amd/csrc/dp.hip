@@ -24,11 +24,12 @@
 namespace ss {
 
 // Row-order distances and their codes, one thread per row; the SlimChunk
-// combine buffer and arrival counters start at zero.  n_pad is a multiple of
-// 64, so a wavefront is either wholly in range or wholly out.
+// combine buffer, the best v of each row (rows the sweep never visits keep
+// 0: no parent) and the arrival counters start at zero.  n_pad is a multiple
+// of 64, so a wavefront is either wholly in range or wholly out.
 __global__ void dp_prep_kernel(int32_t n_pad, int64_t n_chunks, const int32_t* v,
                                const int32_t* dist, int32_t* drow, uint8_t* code, int32_t* acc,
-                               int32_t* arrive) {
+                               int32_t* best, int32_t* arrive) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_chunks) arrive[r] = 0;
   if (r >= n_pad) return;
@@ -36,6 +37,7 @@ __global__ void dp_prep_kernel(int32_t n_pad, int64_t n_chunks, const int32_t* v
   const int32_t d = o >= 0 ? dist[o] : -1;
   drow[r] = d;
   acc[r] = 0;
+  best[r] = 0;
   const uint32_t c = d < 0 ? 3u : (uint32_t)(d % 3);
   const uint32_t c1 = __shfl_down(c, 1), c2 = __shfl_down(c, 2), c3 = __shfl_down(c, 3);
   if ((threadIdx.x & 3) == 0) code[r >> 2] = (uint8_t)(c | (c1 << 2) | (c2 << 4) | (c3 << 6));
@@ -62,7 +64,7 @@ int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unrol
   const int64_t work = std::max<int64_t>(g.n_pad, g.n_chunks);
   const unsigned blocks = (unsigned)((work + 255) / 256);
   dp_prep_kernel<<<blocks, 256, 0, st>>>((int32_t)g.n_pad, g.n_chunks, g.d_v, dist, ws.d, ws.g,
-                                         ws.acc, ws.arrive);
+                                         ws.acc, ws.state, ws.arrive);
   int rc = check_launch("dp_prep_kernel");
   if (rc) return rc;
   LevelArgs a;

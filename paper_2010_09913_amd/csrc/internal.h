@@ -73,6 +73,7 @@ struct Workspace {
   float* rv = nullptr;        // real value at discovery (4 B per row)
   int32_t* acc = nullptr;     // SlimChunk partial combine buffer (4 B per row)
   int32_t* arrive = nullptr;  // SlimChunk arrival counters (4 B per chunk)
+  uint8_t* done = nullptr;    // 1 once every row of the chunk is final (1 B per chunk)
   uint64_t* any = nullptr;    // [kRing] per-level tag (run_id << 32 | level) if it found rows
   unsigned long long* counters = nullptr;  // per-level counters, see LevelArgs::counters
   int64_t counter_words = 0;               // capacity of counters[]
@@ -169,7 +170,7 @@ struct Graph {
   std::vector<int64_t> h_roff;    // [num_graphs + 1] row offset of each graph
   int64_t* d_voff = nullptr;
   uint32_t run_id = 0;
-  ss_tune tune{256, 16, 8, 512, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
+  ss_tune tune{256, 16, 4, 1024, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
   int32_t lds_cap = 0;                // largest LDS prefix the device allows, bytes
   int32_t lds_dev = 0;                // dynamic LDS the device allows one workgroup, bytes
   std::mutex mu;
@@ -194,6 +195,7 @@ struct LevelArgs {
   float* rv;
   int32_t* acc;
   int32_t* arrive;
+  uint8_t* done;     // per chunk: all rows final (nullptr: not kept)
   uint64_t* any;
   // per-level counters of this root: [(level * kCountSlots + slot) * kCountFields + field]
   unsigned long long* counters;

@@ -56,7 +56,13 @@ struct Tropical {
   __device__ static bool settled(Acc acc) { return acc != kInf; }
   __device__ static Acc identity() { return kInf; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.state, a.n_pad * 4u); }
+  using Raw = int32_t;  // the word the live test reads
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.state[row]; }
+  __device__ static bool is_live(const LevelArgs&, Raw w, int32_t) { return w == kInf; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == kInf; }
+  __device__ static bool still_live(const LevelArgs&, int32_t, bool live, bool fresh) {
+    return live && !fresh;
+  }
   // terms 1 + f_{k-1}^c; a value >= k was written in this level and stands for infinity
   __device__ static const void* staged(const LevelArgs& a) { return a.state; }
   template <int U, bool STAGED>
@@ -110,7 +116,13 @@ struct Real {
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0.0f; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 4u); }
+  using Raw = uint32_t;
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.g[row]; }
+  __device__ static bool is_live(const LevelArgs&, Raw w, int32_t) { return w != 0u; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  __device__ static bool still_live(const LevelArgs&, int32_t, bool live, bool fresh) {
+    return live && !fresh;
+  }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
@@ -160,7 +172,13 @@ struct Boolean {
   __device__ static bool settled(Acc acc) { return acc != 0u; }
   __device__ static Acc identity() { return 0u; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad); }
+  using Raw = uint32_t;
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.g[row]; }
+  __device__ static bool is_live(const LevelArgs&, Raw w, int32_t) { return w != 0u; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.g[row] != 0; }
+  __device__ static bool still_live(const LevelArgs&, int32_t, bool live, bool fresh) {
+    return live && !fresh;
+  }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs&, Rsrc r, Stage st, const int32_t (&c)[U],
@@ -218,7 +236,13 @@ struct SelMax {
   __device__ static Rsrc rsrc(const LevelArgs& a) {
     return make_rsrc(a.vin, (uint32_t)(a.n_pad / kC) * 8u);
   }
+  using Raw = int32_t;
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.state[row]; }
+  __device__ static bool is_live(const LevelArgs&, Raw w, int32_t) { return w == 0; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.state[row] == 0; }
+  __device__ static bool still_live(const LevelArgs&, int32_t, bool live, bool fresh) {
+    return live && !fresh;
+  }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
@@ -289,9 +313,19 @@ struct Batch {
   __device__ static bool settled(Acc) { return false; }
   __device__ static Acc identity() { return 0ull; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad * 8u); }
+  using Raw = unsigned long long;
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.vis[row]; }
+  __device__ static bool is_live(const LevelArgs& a, Raw w, int32_t chunk) {
+    const Acc full = a.full[chunk];
+    return (w & full) != full;
+  }
   __device__ static bool live(const LevelArgs& a, int32_t row) {
     const Acc full = a.full[row / kC];
     return (a.vis[row] & full) != full;
+  }
+  // the visited mask post just wrote (this lane's own store)
+  __device__ static bool still_live(const LevelArgs& a, int32_t row, bool, bool) {
+    return live(a, row);
   }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
@@ -345,7 +379,13 @@ struct Dp {
   __device__ static bool settled(Acc acc) { return acc != 0; }
   __device__ static Acc identity() { return 0; }
   __device__ static Rsrc rsrc(const LevelArgs& a) { return make_rsrc(a.vin, a.n_pad / 4u); }
+  using Raw = int32_t;
+  __device__ static Raw raw(const LevelArgs& a, int32_t row) { return a.d[row]; }
+  __device__ static bool is_live(const LevelArgs&, Raw w, int32_t) { return w >= 1; }
   __device__ static bool live(const LevelArgs& a, int32_t row) { return a.d[row] >= 1; }
+  __device__ static bool still_live(const LevelArgs&, int32_t, bool live, bool fresh) {
+    return live && !fresh;
+  }
   __device__ static const void* staged(const LevelArgs& a) { return a.vin; }
   template <int U, bool STAGED>
   __device__ static Acc block(const LevelArgs& a, Rsrc r, Stage st, const int32_t (&c)[U],
@@ -512,6 +552,9 @@ __device__ __forceinline__ uint32_t finish_rows(const LevelArgs& a, int32_t chun
   S::publish(a, chunk, mask, lane);
   if (record && lane == 0 && mask)  // the chunk has a frontier row for the next level
     atomicOr(a.summ + (int64_t)(a.level % 3) * a.summ_words + (chunk >> 5), 1u << (chunk & 31));
+  // a chunk whose rows are all final stays final: later levels skip it
+  // without reading its rows
+  if (a.done && !__any(S::still_live(a, row, live, fresh)) && lane == 0) a.done[chunk] = 1;
   if (fresh) fdeg += (uint64_t)a.deg[row];
   return (uint32_t)__popcll(mask);
 }
@@ -589,6 +632,17 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   const int waves = blockDim.x / kC;
   const Rsrc rs = S::rsrc(a);
   Stage st{lds_stage, 0u};
+  // this wavefront's first 64 work units (see the unit loop below)
+  const int64_t stride = (int64_t)gridDim.x * waves;
+  const int64_t u0 = (int64_t)blockIdx.x * waves + wave;
+  const bool skip_done = a.done != nullptr && a.slimwork != 0;
+  Unit mine{0, 0, 0, 0};
+  bool want = false;
+  {
+    const int64_t uk = u0 + (int64_t)lane * stride;
+    want = uk < n_units;
+    if (want) mine = units[uk];
+  }
   if (a.summ) {
     // clear the summary the next level writes (read by the level before this one)
     uint32_t* next = a.summ + (int64_t)((a.level + 1) % 3) * a.summ_words;
@@ -624,6 +678,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
     }
     __syncthreads();
     st.bytes = a.lds_bytes;
+    st.summ = a.lds_bytes;
     // the filter pays when few chunks hold frontier rows (the same decision
     // in every workgroup: all count the same summary)
     if (have) st.filter = (int64_t)flagged <= (int64_t)a.filter_limit;
@@ -639,23 +694,63 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   uint64_t n_cols = 0, fdeg = 0;
   int32_t max_cl = 0;
 
-  const int64_t stride = (int64_t)gridDim.x * waves;
-  int64_t u = (int64_t)blockIdx.x * waves + wave;
-  Unit w{0, 0, 0, 0};
-  if (u < n_units) w = units[u];
-  for (; u < n_units; u += stride) {
-    // the next unit's descriptor is read while this one is swept
-    Unit wn = w;
-    if (u + stride < n_units) wn = units[u + stride];
+  // Work units u0, u0 + stride, u0 + 2 stride, ... of this wavefront, 64 at a
+  // time: lane k reads the descriptor of the k-th and, for a unit of one
+  // chunk, the chunk's "all rows final" flag, so one ballot names the units
+  // to sweep (a level whose chunks are mostly final pays two memory round
+  // trips per 64 units instead of one per unit).  While one unit is swept,
+  // the next one's chunk extent, degrees and row states are in flight.
+  // (The first batch's descriptors were requested before the LDS staging,
+  // so their latency overlaps it.)
+  for (int64_t b = u0; b < n_units; b += (int64_t)kC * stride) {
+    if (b != u0) {
+      const int64_t uk = b + (int64_t)lane * stride;
+      want = uk < n_units;
+      if (want) mine = units[uk];
+    }
+    if (want && skip_done && mine.c1 == mine.c0 + 1) want = a.done[mine.c0] == 0;
+    uint64_t todo = __ballot(want);
+    // the next unit to sweep and its first chunk's metadata (loads in flight)
+    Unit nw{0, 0, 0, 0};
+    int32_t n_len = 0, n_dg = 0;
+    int64_t n_start = 0;
+    typename S::Raw n_raw{};
+    auto next = [&]() -> bool {
+      if (!todo) return false;
+      const int k = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      nw.c0 = __builtin_amdgcn_readlane(mine.c0, k);
+      nw.c1 = __builtin_amdgcn_readlane(mine.c1, k);
+      nw.j0 = __builtin_amdgcn_readlane(mine.j0, k);
+      nw.j1 = __builtin_amdgcn_readlane(mine.j1, k);
+      n_len = a.cl[nw.c0];
+      n_start = a.cs[nw.c0];
+      n_dg = a.deg[nw.c0 * kC + lane];
+      n_raw = S::raw(a, nw.c0 * kC + lane);
+      return true;
+    };
+    bool more = next();
+    while (more) {
+    const Unit w = nw;
+    const int32_t f_len = n_len, f_dg = n_dg;
+    const int64_t f_start = n_start;
+    const typename S::Raw f_raw = n_raw;
+    more = next();
     const bool piece = (w.c1 == w.c0 + 1);
     for (int32_t c = w.c0; c < w.c1; ++c) {
       const int32_t row = c * kC + lane;
-      // the chunk's extent and the row's degree are read together with its
-      // state, so the column stream starts one memory latency after the unit
-      const int32_t len = a.cl[c];
-      const int64_t start = a.cs[c];
-      const int32_t dg = a.deg[row];
-      const bool live = S::live(a, row);
+      // the first chunk's extent, degrees and states were read ahead; the
+      // other chunks of a packed run read theirs together
+      int32_t len = f_len, dg = f_dg;
+      int64_t start = f_start;
+      typename S::Raw rw = f_raw;
+      if (c != w.c0) {
+        len = a.cl[c];
+        start = a.cs[c];
+        dg = a.deg[row];
+        rw = S::raw(a, row);
+      }
+      const bool live = S::is_live(a, rw, c);
       if (a.slimwork && !__any(live)) continue;  // whole chunk final
       int32_t j0 = 0, j1 = len;
       if (piece) { j0 = w.j0; j1 = w.j1; }
@@ -695,7 +790,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
         }
       }
     }
-    w = wn;
+    }
   }
   flush_counters(a, lane, found, n_chunks, n_cols * kC, max_cl, fdeg);
 }
@@ -1244,9 +1339,12 @@ template <int SEMI>
 __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const int32_t* v,
                             int32_t root_row, void* va, void* vb, int32_t* state, uint8_t* g,
                             int32_t* d, float* rv, int32_t* acc, int32_t* arrive, uint32_t* summ,
-                            int32_t summ_words) {
+                            int32_t summ_words, uint8_t* done) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n_chunks) arrive[r] = 0;
+  if (r < n_chunks) {
+    arrive[r] = 0;
+    if (done) done[r] = 0;
+  }
   if (summ && r < summ_words) {
     // level 0's frontier summary holds the root's chunk; level 1's starts empty
     const int32_t rc = root_row / kC;
@@ -1317,9 +1415,12 @@ __global__ void finalise_kernel(int32_t n, const int32_t* perm, const int32_t* s
 __global__ void batch_init_kernel(int32_t n_pad, int64_t n_chunks, const int32_t* v,
                                   unsigned long long* vis, unsigned long long* fa,
                                   unsigned long long* acc64, int32_t* arrive, uint32_t* summ,
-                                  int32_t summ_words) {
+                                  int32_t summ_words, uint8_t* done) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n_chunks) arrive[r] = 0;
+  if (r < n_chunks) {
+    arrive[r] = 0;
+    if (done) done[r] = 0;
+  }
   if (summ && r < summ_words) {
     // level 0's summary gets the roots' chunks (next kernel); level 1's starts empty
     summ[r] = 0u;
@@ -1404,7 +1505,7 @@ int launch_init(int semiring, const Graph& g, const Workspace& ws, int32_t root_
 #define SS_INIT(S)                                                                             \
   init_kernel<S><<<blocks, 256, 0, st>>>(g.n, g.n_pad, g.n_chunks, g.d_v, root_row, ws.vec_a, \
                                          ws.vec_b, ws.state, ws.g, ws.d, ws.rv, ws.acc,       \
-                                         ws.arrive, summ, ws.summ_words)
+                                         ws.arrive, summ, ws.summ_words, ws.done)
   switch (semiring) {
     case SS_TROPICAL: SS_INIT(SS_TROPICAL); break;
     case SS_REAL: SS_INIT(SS_REAL); break;
@@ -1653,7 +1754,7 @@ int launch_batch_init(const Graph& g, const BatchWorkspace& b, int32_t count, bo
   uint32_t* summ = summary ? g.ws.summ : nullptr;
   batch_init_kernel<<<blocks_for(g.n_pad, 256), 256, 0, st>>>(g.n_pad, g.n_chunks, g.d_v, b.vis,
                                                               b.fa, b.acc64, g.ws.arrive, summ,
-                                                              g.ws.summ_words);
+                                                              g.ws.summ_words, g.ws.done);
   int rc = check_launch("batch_init_kernel");
   if (rc || count == 0) return rc;
   batch_roots_kernel<<<blocks_for(count, 256), 256, 0, st>>>(count, b.root_rows, b.slots, b.vis,
