@@ -304,6 +304,7 @@ struct RunPlan {
   bool level_events = false;  // timing: events around every level launch too
   bool summ = false;          // frontier summaries filter the gathers (plain runs)
   int32_t filter_limit = 0;   // most flagged chunks for which a level filters
+  int32_t prefix_words = 0;   // summary words covering the chunks of the LDS prefix
   int32_t slimwork = 2;
   int32_t schedule = 0;
   uint32_t lds_bytes = 0;
@@ -398,6 +399,9 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
                                                     : (int64_t)p->lds_bytes / 4;
     const int64_t nc = g.n_chunks;
     const int64_t in_chunks = std::min<int64_t>(rows / kC, nc);
+    // chunks with rows in the prefix (a partly covered one included)
+    const int64_t cover = std::min<int64_t>((rows + kC - 1) / kC, nc);
+    p->prefix_words = (int32_t)((cover + 31) / 32);
     const double total = nc > 0 ? (double)g.h_chunk_deg[(size_t)nc] : 0.0;
     const double outside = total > 0 ? 1.0 - (double)g.h_chunk_deg[(size_t)in_chunks] / total : 0.0;
     const double frac = outside > kFilterTau ? 1.0 - kFilterTau / outside : 0.0;
@@ -483,6 +487,7 @@ static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, cons
   a.summ = p.summ ? ws.summ : nullptr;
   a.summ_words = ws.summ_words;
   a.filter_limit = p.filter_limit;
+  a.prefix_words = p.prefix_words;
   if (p.schedule) {
     a.variant = g.ws.variant;
     for (int v = 0; v < kPullVariants; ++v) {

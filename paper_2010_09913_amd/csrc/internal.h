@@ -222,6 +222,7 @@ struct LevelArgs {
   uint32_t* summ;      // frontier summaries (Workspace::summ) or nullptr: no gather filter
   int32_t summ_words;
   int32_t filter_limit;  // filter while at most this many chunks hold frontier rows
+  int32_t prefix_words;  // summary words that cover the chunks of the LDS prefix's rows
   int32_t level;     // k >= 1
   int32_t slimwork;
   int32_t count_stats;

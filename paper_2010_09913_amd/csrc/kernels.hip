@@ -48,6 +48,8 @@ __device__ __forceinline__ uint64_t level_tag(uint32_t run_id, int32_t level) {
 // diagonal and infinity elsewhere.  The frontier is the distance vector.
 struct Tropical {
   static constexpr bool kSingleRoot = true;
+  static constexpr bool kBitmapFrontier = false;
+  __device__ static void skip_chunk(const LevelArgs&, int32_t) {}
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -108,6 +110,8 @@ struct Tropical {
 // exact in fp32.
 struct Real {
   static constexpr bool kSingleRoot = true;
+  static constexpr bool kBitmapFrontier = false;
+  __device__ static void skip_chunk(const LevelArgs&, int32_t) {}
   using Acc = float;
   // a row's value is known only after all its terms (a sum of frontier terms)
   static constexpr bool kFirstHitFinal = false;
@@ -164,6 +168,8 @@ struct Real {
 // Boolean (|, &): x_k = A (x) f_{k-1}; f_k = x_k & g_k with a uint8 frontier.
 struct Boolean {
   static constexpr bool kSingleRoot = true;
+  static constexpr bool kBitmapFrontier = false;
+  __device__ static void skip_chunk(const LevelArgs&, int32_t) {}
   using Acc = uint32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -226,6 +232,14 @@ struct Boolean {
 // evaluated exactly while the gathered array is 32 times smaller.
 struct SelMax {
   static constexpr bool kSingleRoot = true;
+  // the frontier is a bitmap with one word per chunk; in a scheduled run a
+  // chunk the level skips gets a zero word, so every chunk's word tells
+  // exactly which rows entered at this level (a push level after it scans
+  // the words instead of every row's distance)
+  static constexpr bool kBitmapFrontier = true;
+  __device__ static void skip_chunk(const LevelArgs& a, int32_t chunk) {
+    static_cast<uint64_t*>(a.vout)[chunk] = 0ull;
+  }
   using Acc = int32_t;
   // the first product term a row receives is its final value
   static constexpr bool kFirstHitFinal = true;
@@ -305,6 +319,8 @@ struct SelMax {
 // slot its graph uses has reached it.
 struct Batch {
   static constexpr bool kSingleRoot = false;
+  static constexpr bool kBitmapFrontier = false;
+  __device__ static void skip_chunk(const LevelArgs&, int32_t) {}
   using Acc = unsigned long long;
   // a row's masks are known only after all its terms (an OR over neighbours)
   static constexpr bool kFirstHitFinal = false;
@@ -368,6 +384,8 @@ struct Batch {
 // holds row distances); each row's best v goes to `state`.
 struct Dp {
   static constexpr bool kSingleRoot = true;
+  static constexpr bool kBitmapFrontier = false;
+  __device__ static void skip_chunk(const LevelArgs&, int32_t) {}
   using Acc = int32_t;
   // the first hit is the largest qualifying ID
   static constexpr bool kFirstHitFinal = true;
@@ -653,35 +671,50 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   // the previous level left a summary only if it used one itself
   const bool have = a.summ && a.summ[3 * (int64_t)a.summ_words + (a.level - 1) % 3] != 0u;
   if (STAGED) {
-    // copy the vector's first a.lds_bytes (a multiple of 16) into LDS, then
-    // the previous level's frontier summary behind it, counting its set bits
-    __shared__ uint32_t flagged;
+    // The previous level's frontier summary (if it left one) goes to LDS
+    // behind the prefix's place, and its set bits are counted, in all and
+    // among the chunks the prefix covers.  The level filters its gathers by
+    // it when few chunks hold frontier rows (the same decision in every
+    // workgroup: all count the same summary).  The vector's first
+    // a.lds_bytes (a multiple of 16) are then copied into LDS, unless the
+    // level filters and no chunk the prefix covers holds a frontier row: then
+    // every term the prefix would serve is the identity and is not read.
+    __shared__ uint32_t flagged, flagged_prefix;
+    st.summ = a.lds_bytes;
+    bool stage = true;
     if (have) {
-      if (threadIdx.x == 0) flagged = 0u;
+      if (threadIdx.x == 0) {
+        flagged = 0u;
+        flagged_prefix = 0u;
+      }
       __syncthreads();
-    }
-    const uint4* src = static_cast<const uint4*>(S::staged(a));
-    uint4* dst = reinterpret_cast<uint4*>(lds_stage);
-    for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
-    if (have) {
       const uint32_t* prev = a.summ + (int64_t)((a.level - 1) % 3) * a.summ_words;
       uint32_t* sd = reinterpret_cast<uint32_t*>(lds_stage + a.lds_bytes);
-      uint32_t cnt = 0u;
+      uint32_t cnt = 0u, cnt_p = 0u;
       for (int32_t i = threadIdx.x; i < a.summ_words; i += blockDim.x) {
         const uint32_t w = prev[i];
         sd[i] = w;
         cnt += (uint32_t)__popc(w);
+        if (i < a.prefix_words) cnt_p += (uint32_t)__popc(w);
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+      for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cnt_p += __shfl_xor(cnt_p, off);
+      }
       if (lane == 0 && cnt) atomicAdd(&flagged, cnt);
+      if (lane == 0 && cnt_p) atomicAdd(&flagged_prefix, cnt_p);
+      __syncthreads();
+      st.filter = (int64_t)flagged <= (int64_t)a.filter_limit;
+      stage = !st.filter || flagged_prefix != 0u;
     }
-    __syncthreads();
-    st.bytes = a.lds_bytes;
-    st.summ = a.lds_bytes;
-    // the filter pays when few chunks hold frontier rows (the same decision
-    // in every workgroup: all count the same summary)
-    if (have) st.filter = (int64_t)flagged <= (int64_t)a.filter_limit;
+    if (stage) {
+      const uint4* src = static_cast<const uint4*>(S::staged(a));
+      uint4* dst = reinterpret_cast<uint4*>(lds_stage);
+      for (uint32_t i = threadIdx.x; i < a.lds_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+      __syncthreads();
+      st.bytes = a.lds_bytes;
+    }
   }
   // A level records its own frontier summary only when it used the filter:
   // after a level with a wide frontier the next one is usually wide too, and
@@ -708,7 +741,10 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       want = uk < n_units;
       if (want) mine = units[uk];
     }
-    if (want && skip_done && mine.c1 == mine.c0 + 1) want = a.done[mine.c0] == 0;
+    if (want && skip_done && mine.c1 == mine.c0 + 1 && a.done[mine.c0] != 0) {
+      want = false;
+      if (a.variant) S::skip_chunk(a, mine.c0);  // a push level may follow
+    }
     uint64_t todo = __ballot(want);
     // the next unit to sweep and its first chunk's metadata (loads in flight)
     Unit nw{0, 0, 0, 0};
@@ -751,7 +787,10 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
         rw = S::raw(a, row);
       }
       const bool live = S::is_live(a, rw, c);
-      if (a.slimwork && !__any(live)) continue;  // whole chunk final
+      if (a.slimwork && !__any(live)) {  // whole chunk final
+        if (a.variant && lane == 0) S::skip_chunk(a, c);
+        continue;
+      }
       int32_t j0 = 0, j1 = len;
       if (piece) { j0 = w.j0; j1 = w.j1; }
       if (j0 == 0) {
@@ -937,10 +976,16 @@ __device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw
     const int64_t i = base + lane;
     int32_t u = -1;
     if (i < nq) {
-      if (!scan)
+      if (!scan) {
         u = a.q_in[i];
-      else if (S::entered(a, (int32_t)i, a.level - 1))
+      } else if (S::kBitmapFrontier) {
+        // the previous level's frontier word of this chunk (one load for the
+        // wavefront's 64 rows instead of one distance per row)
+        const uint64_t wd = static_cast<const uint64_t*>(a.vin)[base >> 6];
+        if ((wd >> lane) & 1ull) u = (int32_t)i;
+      } else if (S::entered(a, (int32_t)i, a.level - 1)) {
         u = (int32_t)i;
+      }
     }
     const int32_t du = u >= 0 ? a.deg[u] : 0;
     const bool big = du > kPushLaneMax;
@@ -1074,6 +1119,7 @@ struct SchedShared {
   double sums[3];
   float mf, mu;
   int32_t v, stop;
+  int32_t need;  // model's choice + 1 when the training-domain test must decide, else 0
 };
 
 // Level k's variant, from level k-1's counters, computed by a whole
@@ -1127,29 +1173,11 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     if (writer && t == 0) s.variant[k % kRing] = kStop;
     return kStop;
   }
-  bool use_model = (s.mode == 1) && s.model;
-  if (use_model && s.anchors) {
-    // nearest anchor: threads 0..63 each scan a strided share, then a min
-    // tree (min is exact, so every workgroup gets the same value)
-    if (t < 64) {
-      float best = INFINITY;
-      for (int i = t; i < s.n_anchors; i += 64) {
-        float d2 = 0.f;
-        for (int f = 0; f < kFeatures; ++f) {
-          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
-          d2 = fmaf(df, df, d2);
-        }
-        best = d2 < best ? d2 : best;
-      }
-      sh.near[t] = best;
-    }
-    __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-      if (t < w) sh.near[t] = sh.near[t + w] < sh.near[t] ? sh.near[t + w] : sh.near[t];
-      __syncthreads();
-    }
-    use_model = sh.near[0] <= s.tau2;  // outside the training domain: the heuristic decides
-  }
+  // Learned: the MLP scores the four variants first.  Where its choice is
+  // the fixed heuristic's, that is the variant and the training domain needs
+  // no test; otherwise the level takes the model's choice only if its
+  // features lie within tau of an anchor of the training data.
+  const bool use_model = (s.mode == 1) && s.model;
   if (use_model) {
     const float* W1 = s.model;
     const float* b1 = W1 + 32 * kFeatures;
@@ -1177,33 +1205,59 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     __syncthreads();
   }
   if (t == 0) {
-    int32_t v;
+    // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
+    // pull once the frontier's edges exceed 1/14 of the unvisited edges
+    const int32_t h = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
+    int32_t v = h;
+    sh.need = 0;
     if (s.mode >= 3) {
       v = s.mode - 3;
-    } else {
-      bool finite = use_model;
-      if (use_model)
-        for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(sh.out[i]);
+    } else if (use_model) {
+      bool finite = true;
+      for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(sh.out[i]);
       if (finite) {
-        v = 0;
+        int32_t m = 0;
         for (int i = 1; i < kVariants; ++i)
-          if (sh.out[i] < sh.out[v]) v = i;
-      } else {
-        // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
-        // pull once the frontier's edges exceed 1/14 of the unvisited edges
-        v = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
+          if (sh.out[i] < sh.out[m]) m = i;
+        if (m == h || !s.anchors) v = m;
+        else sh.need = m + 1;  // the domain test decides between m and h
       }
     }
     sh.v = v;
-    if (writer) {
-      s.variant[k % kRing] = v;
-      if (s.log && k <= s.log_cap) {
-        float* L = s.log + (int64_t)(k - 1) * 12;
-        for (int i = 0; i < kFeatures; ++i) L[i] = sh.x[i];
-        for (int i = 0; i < kVariants; ++i) L[kFeatures + i] = use_model ? sh.out[i] : 0.f;
-        L[10] = (float)v;
-        L[11] = (float)k;
+  }
+  __syncthreads();
+  if (sh.need) {
+    // nearest anchor: threads 0..63 each scan a strided share, then a min
+    // tree (min is exact, so every workgroup gets the same value)
+    if (t < 64) {
+      float best = INFINITY;
+      for (int i = t; i < s.n_anchors; i += 64) {
+        float d2 = 0.f;
+        for (int f = 0; f < kFeatures; ++f) {
+          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
+          d2 = fmaf(df, df, d2);
+        }
+        best = d2 < best ? d2 : best;
       }
+      sh.near[t] = best;
+    }
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (t < w) sh.near[t] = sh.near[t + w] < sh.near[t] ? sh.near[t + w] : sh.near[t];
+      __syncthreads();
+    }
+    // outside the training domain the heuristic's choice stands
+    if (t == 0 && sh.near[0] <= s.tau2) sh.v = sh.need - 1;
+  }
+  if (t == 0 && writer) {
+    const int32_t v = sh.v;
+    s.variant[k % kRing] = v;
+    if (s.log && k <= s.log_cap) {
+      float* L = s.log + (int64_t)(k - 1) * 12;
+      for (int i = 0; i < kFeatures; ++i) L[i] = sh.x[i];
+      for (int i = 0; i < kVariants; ++i) L[kFeatures + i] = use_model ? sh.out[i] : 0.f;
+      L[10] = (float)v;
+      L[11] = (float)k;
     }
   }
   __syncthreads();
