@@ -456,7 +456,9 @@ int slimsell_sched_load(const float* weights, int64_t count);
 /* Remove the model (learned scheduling then uses the fixed heuristic). */
 int slimsell_sched_clear(void);
 /* Per-level record of the last scheduled run on g: host float[cap][12] =
- * 6 features, 4 scores (0 without a model), chosen variant, level.  *levels
+ * 6 features, 4 scores, chosen variant, level.  The scores are 0 without a
+ * model and for a level outside the training domain's box (the anchors'
+ * bounding box widened by tau), which the model does not score.  *levels
  * receives the records written: the last scheduled run's level count (its
  * iterations, at most min(n + 2, 65536)), clamped to cap; 0 before any
  * scheduled run. */

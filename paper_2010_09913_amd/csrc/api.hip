@@ -13,6 +13,7 @@
 #include <cstring>
 #include <immintrin.h>
 #include <new>
+#include <queue>
 #include <string>
 #include <thread>
 
@@ -66,8 +67,17 @@ static int dalloc(T** p, int64_t count) {
 static void release_units(UnitList& u) {
   if (u.d_units) (void)hipFree(u.d_units);
   if (u.d_pieces) (void)hipFree(u.d_pieces);
+  if (u.d_bundle) (void)hipFree(u.d_bundle);
+  if (u.d_arrive2) (void)hipFree(u.d_arrive2);
+  for (auto& kv : u.assign) {
+    if (kv.second.d_units) (void)hipFree(kv.second.d_units);
+    if (kv.second.d_off) (void)hipFree(kv.second.d_off);
+  }
+  u.assign.clear();
   u.d_units = nullptr;
   u.d_pieces = nullptr;
+  u.d_bundle = nullptr;
+  u.d_arrive2 = nullptr;
 }
 
 static void release_graph(Graph* g) {
@@ -158,6 +168,9 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
   UnitList ul;
   ul.split_len = split;
   ul.pack_cols = pack;
+  ul.h_units = units;
+  ul.h_cols.resize(units.size());
+  for (size_t i = 0; i < units.size(); ++i) ul.h_cols[i] = cost(units[i]);
   ul.count = (int64_t)units.size();
   ul.split_chunks = split_chunks;
   int rc = dalloc(&ul.d_units, std::max<int64_t>(1, ul.count));
@@ -174,8 +187,82 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) { release_units(ul); return hip_fail(e, "upload pieces"); }
   }
+  // arrival bundles of the split chunks
+  std::vector<int32_t> bundle((size_t)std::max<int64_t>(nc, 1), 0);
+  int64_t bundles = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    bundle[(size_t)c] = (int32_t)bundles;
+    if (pieces[(size_t)c] > 1) bundles += (pieces[(size_t)c] + kBundle - 1) / kBundle;
+  }
+  ul.bundles = bundles;
+  rc = dalloc(&ul.d_bundle, std::max<int64_t>(1, nc));
+  if (!rc) rc = dalloc(&ul.d_arrive2, std::max<int64_t>(1, bundles));
+  if (rc) { release_units(ul); return rc; }
+  {
+    hipError_t e = hipMemcpy(ul.d_bundle, bundle.data(), sizeof(int32_t) * bundle.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemset(ul.d_arrive2, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(1, bundles));
+    if (e != hipSuccess) { release_units(ul); return hip_fail(e, "upload arrival bundles"); }
+  }
   auto res = g.units.emplace(key, ul);
   *out = &res.first->second;
+  return SS_OK;
+}
+
+// A unit's cost for the assignment: its columns plus a fixed per-unit cost
+// (reading its descriptor, chunk extent and row states before the first
+// column, and post-processing its rows), in columns: measured on R-MAT s22,
+// a unit of a few columns keeps a wavefront about as long as ten columns of a
+// long piece do.
+constexpr int64_t kUnitCost = 12;
+
+// The per-wavefront assignment of a unit list for a grid of W wavefronts:
+// units, longest first, each to the wavefront with the least work so far
+// (the longest-processing-time rule); ties go to the lower wavefront.
+static int get_assignment(UnitList& ul, int64_t W, const UnitList::Assignment** out,
+                          bool lookup_only) {
+  *out = nullptr;
+  auto it = ul.assign.find(W);
+  if (it != ul.assign.end()) {
+    *out = &it->second;
+    return SS_OK;
+  }
+  if (lookup_only || W < 1 || W > INT32_MAX) return SS_OK;  // round-robin instead
+  const std::vector<Unit>& units = ul.h_units;
+  const int64_t n = (int64_t)units.size();
+  std::vector<int32_t> owner((size_t)n);
+  using Load = std::pair<int64_t, int64_t>;  // (work so far, wavefront)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int64_t w = 0; w < std::min<int64_t>(W, std::max<int64_t>(n, 1)); ++w) heap.push({0, w});
+  std::vector<int64_t> per((size_t)W + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t cols = ul.h_cols[(size_t)i];
+    Load top = heap.top();
+    heap.pop();
+    owner[(size_t)i] = (int32_t)top.second;
+    ++per[(size_t)top.second + 1];
+    heap.push({top.first + cols + kUnitCost, top.second});
+  }
+  for (int64_t w = 0; w < W; ++w) per[(size_t)w + 1] += per[(size_t)w];
+  std::vector<Unit> order((size_t)std::max<int64_t>(n, 1));
+  std::vector<int64_t> fill(per.begin(), per.end() - 1);
+  for (int64_t i = 0; i < n; ++i) order[(size_t)fill[(size_t)owner[(size_t)i]]++] = units[(size_t)i];
+  std::vector<int32_t> off(per.begin(), per.end());
+  UnitList::Assignment as;
+  int rc = dalloc(&as.d_units, (int64_t)order.size());
+  if (!rc) rc = dalloc(&as.d_off, W + 1);
+  if (!rc && (hipMemcpy(as.d_units, order.data(), sizeof(Unit) * order.size(),
+                        hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(as.d_off, off.data(), sizeof(int32_t) * off.size(),
+                        hipMemcpyHostToDevice) != hipSuccess))
+    rc = set_error(SS_EHIP, "upload of the unit assignment failed");
+  if (rc) {
+    if (as.d_units) (void)hipFree(as.d_units);
+    if (as.d_off) (void)hipFree(as.d_off);
+    return rc;
+  }
+  *out = &ul.assign.emplace(W, as).first->second;
   return SS_OK;
 }
 
@@ -309,6 +396,7 @@ struct RunPlan {
   int32_t schedule = 0;
   uint32_t lds_bytes = 0;
   UnitList* ul = nullptr;
+  const UnitList::Assignment* as = nullptr;  // per-wavefront units of the level launch
   UnitList* vul[kPullVariants] = {nullptr, nullptr, nullptr};  // pull variants
   bool has_model = false;
   int32_t n_anchors = 0;  // training-domain anchors carried by the model
@@ -415,6 +503,13 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   p->schedule = o->schedule;
   int rc = get_units(g, split, pack, &p->ul, no_alloc);
   if (rc) return rc;
+  // the level launch's grid, and its per-wavefront assignment of the units
+  // (an allocation-free call uses a prepared one or none)
+  {
+    const int64_t W = level_groups(p->ul->count, p->waves, p->max_groups) * p->waves;
+    // with no more units than wavefronts each takes one (or none): no table
+    if (W < p->ul->count && (rc = get_assignment(*p->ul, W, &p->as, no_alloc))) return rc;
+  }
   if (p->schedule) {
     const int32_t vsplit[kPullVariants] = {0, 256, 1024};
     for (int v = 0; v < kPullVariants; ++v)
@@ -470,6 +565,13 @@ static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, cons
   a.units = p.ul->d_units;
   a.pieces = p.ul->d_pieces;
   a.n_units = p.ul->count;
+  a.bundle = p.ul->d_bundle;
+  a.arrive2 = p.ul->d_arrive2;
+  a.piece_cols = p.ul->split_len;
+  if (p.as) {
+    a.units = p.as->d_units;
+    a.wave_off = p.as->d_off;
+  }
   a.state = ws.state;
   a.g = ws.g;
   a.d = ws.d;
@@ -494,6 +596,9 @@ static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, cons
       a.vunits[v] = p.vul[v]->d_units;
       a.vpieces[v] = p.vul[v]->d_pieces;
       a.vn_units[v] = p.vul[v]->count;
+      a.vbundle[v] = p.vul[v]->d_bundle;
+      a.varrive2[v] = p.vul[v]->d_arrive2;
+      a.vpiece_cols[v] = p.vul[v]->split_len;
     }
     a.qn = g.ws.qn;
     a.ring_ctr = g.ws.ring_ctr;
@@ -510,7 +615,7 @@ static int check_sched_args(const LevelArgs& a) {
   if (!a.variant || !a.qn || !a.ring_ctr || !a.segs || !a.seg_n)
     return set_error(SS_EHIP, "internal: scheduled run without its queue buffers");
   for (int v = 0; v < kPullVariants; ++v)
-    if (!a.vunits[v] || !a.vpieces[v])
+    if (!a.vunits[v] || !a.vpieces[v] || !a.vbundle[v] || !a.varrive2[v])
       return set_error(SS_EHIP, "internal: scheduled run without its work units");
   return SS_OK;
 }
@@ -531,6 +636,7 @@ static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
   sl.sums = g.ws.sched_sums;
   sl.model = p.has_model ? g.ws.model : nullptr;
   sl.anchors = p.n_anchors ? g.ws.model + kModelSize + 2 : nullptr;
+  sl.box = p.n_anchors ? g.ws.model + kModelSize + 2 + (int64_t)p.n_anchors * kFeatures : nullptr;
   sl.n_anchors = p.n_anchors;
   sl.tau2 = p.tau * p.tau;
   sl.log = g.ws.sched_log;
@@ -555,6 +661,7 @@ static int run_persistent(Graph& g, const RunPlan& p, int policy, LevelArgs a, v
     rate_khz = 100000;
   const uint64_t limit = (uint64_t)rate_khz * 1000ull * 5ull;  // 5 s per barrier wait
   a.count_stats = p.counting ? 1 : 0;
+  a.wave_off = nullptr;  // the persistent grid deals the units round-robin
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p.level_events) {
     if ((rc = pool_event(g, log->next_ev++, &e0))) return rc;
@@ -885,8 +992,30 @@ int slimsell_sched_load(const float* w, int64_t count) {
     for (int64_t i = kModelSize + 2; i < count; ++i)
       if (!std::isfinite(w[i])) return set_error(SS_EINVAL, "model anchors must be finite");
   }
+  std::vector<float> m(w, w + count);
+  if (count > kModelSize) {
+    // the anchors' box widened by tau, plus a relative margin that keeps
+    // the float distance of any level outside it above tau^2 after rounding
+    const float tau = w[kModelSize];
+    const int64_t K = (count - kModelSize - 2) / kFeatures;
+    float lo[kFeatures], hi[kFeatures];
+    for (int f = 0; f < kFeatures; ++f) {
+      lo[f] = INFINITY;
+      hi[f] = -INFINITY;
+      for (int64_t a = 0; a < K; ++a) {
+        const float x = w[kModelSize + 2 + a * kFeatures + f];
+        lo[f] = std::min(lo[f], x);
+        hi[f] = std::max(hi[f], x);
+      }
+      const float r = tau * 1.001f + 1e-6f * std::max(std::fabs(lo[f]), std::fabs(hi[f]));
+      lo[f] -= r;
+      hi[f] += r;
+    }
+    m.insert(m.end(), lo, lo + kFeatures);
+    m.insert(m.end(), hi, hi + kFeatures);
+  }
   std::lock_guard<std::mutex> lk(g_model_mu);
-  g_model.assign(w, w + count);
+  g_model.swap(m);
   g_model_version = ++g_model_counter;
   return SS_OK;
 }
@@ -1009,6 +1138,10 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
     const int32_t sp = g->tune.split_len;
     const int32_t pack = g->tune.pack_cols < 0 ? (sp > 0 ? sp : 0) : g->tune.pack_cols;
     rc = get_units(*g, g->tune.split_len, pack, &ul);
+    const UnitList::Assignment* as = nullptr;
+    const int w = g->tune.waves_per_group;
+    const int64_t W = level_groups(ul ? ul->count : 0, w, g->tune.max_groups) * w;
+    if (!rc && W < ul->count) rc = get_assignment(*ul, W, &as, false);
   }
   if (!rc) rc = dalloc(&g->d_voff, 2);
   if (!rc && hipMemcpy(g->d_voff, g->h_voff.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice) !=
@@ -1064,7 +1197,13 @@ int slimsell_tune_set(ss_graph* g, const ss_tune* t) {
   SS_HIP(hipSetDevice(g->device));
   UnitList* ul = nullptr;
   const int32_t sp = t->split_len;
-  return get_units(*g, sp, t->pack_cols < 0 ? (sp > 0 ? sp : 0) : t->pack_cols, &ul);
+  int rc = get_units(*g, sp, t->pack_cols < 0 ? (sp > 0 ? sp : 0) : t->pack_cols, &ul);
+  const UnitList::Assignment* as = nullptr;
+  if (!rc) {
+    const int64_t W = level_groups(ul->count, w, t->max_groups) * w;
+    if (W < ul->count) rc = get_assignment(*ul, W, &as, false);
+  }
+  return rc;
 }
 
 int slimsell_tune_get(const ss_graph* g, ss_tune* t) {

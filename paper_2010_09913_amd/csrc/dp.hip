@@ -77,6 +77,9 @@ int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unrol
   a.units = ul.d_units;
   a.pieces = ul.d_pieces;
   a.n_units = ul.count;
+  a.bundle = ul.d_bundle;
+  a.arrive2 = ul.d_arrive2;
+  a.piece_cols = ul.split_len;
   a.vin = ws.g;       // the codes
   a.state = ws.state; // best v per row
   a.d = ws.d;         // row distances

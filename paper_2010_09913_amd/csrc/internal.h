@@ -60,7 +60,34 @@ struct UnitList {
   int64_t split_chunks = 0;
   Unit* d_units = nullptr;      // device [count]
   int32_t* d_pieces = nullptr;  // device [n_chunks] pieces per chunk (1 = unsplit)
+  // The pieces of a split chunk arrive in bundles of kBundle consecutive
+  // pieces: a piece counts itself in its bundle's counter, the last piece of
+  // a bundle counts the bundle in the chunk's counter, and the last bundle
+  // post-processes the chunk, so no counter takes more than kBundle, or the
+  // chunk's bundle count, atomics per level.
+  std::vector<Unit> h_units;    // host copy of d_units (longest first)
+  std::vector<int64_t> h_cols;  // columns of each unit
+  int32_t* d_bundle = nullptr;  // device [n_chunks] first bundle counter of a split chunk
+  int32_t* d_arrive2 = nullptr; // device [bundles] bundle counters (zero between levels)
+  int64_t bundles = 0;
+  // Per-wavefront assignments of the units for a grid of W wavefronts (by
+  // W): the units reordered so that wavefront w's are [off[w], off[w + 1]),
+  // chosen longest first onto the least-loaded wavefront.
+  struct Assignment {
+    Unit* d_units = nullptr;
+    int32_t* d_off = nullptr;
+  };
+  std::map<int64_t, Assignment> assign;
 };
+
+// Workgroups of a level launch over n_units work units.
+inline int64_t level_groups(int64_t n_units, int waves, int64_t max_groups) {
+  int64_t groups = (n_units + waves - 1) / waves;
+  if (groups < 1) groups = 1;
+  if (max_groups > 0 && groups > max_groups) groups = max_groups;
+  return groups;
+}
+constexpr int32_t kBundle = 16;  // pieces per arrival bundle
 
 // Device workspace reused by every BFS on a graph.
 struct Workspace {
@@ -133,9 +160,12 @@ constexpr int kModelSize = 6 * 32 + 32 + 32 * 32 + 32 + 32 * 4 + 4;  // 1412 par
 constexpr int kFeatures = 6;
 // A model may carry its training domain after the parameters: tau, K, then K
 // feature vectors (anchors); a level farther than tau from every anchor falls
-// back to the fixed heuristic.
+// back to the fixed heuristic.  The library appends the anchors' bounding box
+// widened by tau (6 lower, then 6 upper bounds): a level outside it is
+// farther than tau from every anchor, which settles the test without the
+// model or the anchor scan.
 constexpr int kMaxAnchors = 1024;
-constexpr int kModelCap = kModelSize + 2 + kMaxAnchors * kFeatures;
+constexpr int kModelCap = kModelSize + 2 + kMaxAnchors * kFeatures + 2 * kFeatures;
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
 
 struct Graph {
@@ -170,7 +200,7 @@ struct Graph {
   std::vector<int64_t> h_roff;    // [num_graphs + 1] row offset of each graph
   int64_t* d_voff = nullptr;
   uint32_t run_id = 0;
-  ss_tune tune{256, 16, 4, 1024, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
+  ss_tune tune{128, 16, 4, 512, 0, 64};  // launch configuration (slimsell_tune_set / autotune)
   int32_t lds_cap = 0;                // largest LDS prefix the device allows, bytes
   int32_t lds_dev = 0;                // dynamic LDS the device allows one workgroup, bytes
   std::mutex mu;
@@ -187,6 +217,12 @@ struct LevelArgs {
   const Unit* units;
   const int32_t* pieces;
   int64_t n_units;
+  const int32_t* bundle;   // per chunk: first bundle counter (split chunks)
+  int32_t* arrive2;        // bundle counters
+  int32_t piece_cols;      // columns per piece (the split length); 0 = no split
+  // per-wavefront unit ranges [wave_off[w], wave_off[w + 1]) of `units` for
+  // the launch grid's wavefronts (level_groups), or nullptr: round-robin
+  const int32_t* wave_off;
   const void* vin;   // frontier read this level (gathered)
   void* vout;        // frontier written this level
   int32_t* state;    // p for sel-max; f for tropical (single buffer)
@@ -205,6 +241,9 @@ struct LevelArgs {
   const Unit* vunits[kPullVariants];
   const int32_t* vpieces[kPullVariants];
   int64_t vn_units[kPullVariants];
+  const int32_t* vbundle[kPullVariants];
+  int32_t* varrive2[kPullVariants];
+  int32_t vpiece_cols[kPullVariants];
   const int32_t* q_in;   // frontier rows of the previous level
   int32_t* q_out;        // frontier rows of this level
   int32_t* qn;           // [kRing] queue lengths
@@ -245,6 +284,7 @@ struct SchedLaunch {
   double* sums;
   const float* model;
   const float* anchors;   // training-domain anchors [n_anchors][6] or nullptr
+  const float* box;       // [12] their box widened by tau (lower, upper) or nullptr
   int32_t n_anchors;
   float tau2;             // squared distance beyond which the heuristic decides
   float* log;

@@ -644,22 +644,39 @@ __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uin
 template <class S, int U, bool STAGED, bool VAL = false>
 __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units,
                                            const int32_t* pieces, int64_t n_units,
+                                           const int32_t* bundle, int32_t* arrive2,
+                                           int32_t piece_cols, const int32_t* wave_off,
                                            uint8_t* lds_stage) {
   const int lane = threadIdx.x & (kC - 1);
   const int wave = threadIdx.x / kC;
   const int waves = blockDim.x / kC;
   const Rsrc rs = S::rsrc(a);
   Stage st{lds_stage, 0u};
-  // this wavefront's first 64 work units (see the unit loop below)
-  const int64_t stride = (int64_t)gridDim.x * waves;
-  const int64_t u0 = (int64_t)blockIdx.x * waves + wave;
-  const bool skip_done = a.done != nullptr && a.slimwork != 0;
-  Unit mine{0, 0, 0, 0};
-  bool want = false;
-  {
-    const int64_t uk = u0 + (int64_t)lane * stride;
-    want = uk < n_units;
-    if (want) mine = units[uk];
+  // This wavefront's work units: with a per-wavefront assignment (wave_off)
+  // the consecutive units [wave_off[w], wave_off[w + 1]), else units w,
+  // w + W, w + 2 W, ... of the grid's W wavefronts.  Its first 64 are read
+  // here (see the unit loop below).
+  const int64_t gw = (int64_t)blockIdx.x * waves + wave;
+  int64_t r0 = gw, step = (int64_t)gridDim.x * waves, count = 0;
+  if (wave_off) {
+    r0 = wave_off[gw];
+    step = 1;
+    count = wave_off[gw + 1] - r0;
+  } else if (gw < n_units) {
+    count = (n_units - gw + step - 1) / step;
+  }
+  // (a wavefront with a single unit learns as much from the unit's row
+  // states, which it reads anyway, one dependent load sooner)
+  const bool skip_done = a.done != nullptr && a.slimwork != 0 && count > 1;
+  // lane k's unit: its first chunk, and whether it is a single chunk (or a
+  // piece of one), whose flag may retire it
+  int32_t mine_c0 = 0;
+  bool mine_one = false;
+  bool want = lane < count;
+  if (want) {
+    const Unit u = units[r0 + (int64_t)lane * step];
+    mine_c0 = u.c0;
+    mine_one = u.c1 == u.c0 + 1;
   }
   if (a.summ) {
     // clear the summary the next level writes (read by the level before this one)
@@ -727,23 +744,25 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
   uint64_t n_cols = 0, fdeg = 0;
   int32_t max_cl = 0;
 
-  // Work units u0, u0 + stride, u0 + 2 stride, ... of this wavefront, 64 at a
-  // time: lane k reads the descriptor of the k-th and, for a unit of one
-  // chunk, the chunk's "all rows final" flag, so one ballot names the units
-  // to sweep (a level whose chunks are mostly final pays two memory round
-  // trips per 64 units instead of one per unit).  While one unit is swept,
-  // the next one's chunk extent, degrees and row states are in flight.
-  // (The first batch's descriptors were requested before the LDS staging,
-  // so their latency overlaps it.)
-  for (int64_t b = u0; b < n_units; b += (int64_t)kC * stride) {
-    if (b != u0) {
-      const int64_t uk = b + (int64_t)lane * stride;
-      want = uk < n_units;
-      if (want) mine = units[uk];
+  // This wavefront's units 64 at a time: lane k reads the descriptor of the
+  // k-th and, for a unit of one chunk, the chunk's "all rows final" flag, so
+  // one ballot names the units to sweep (a level whose chunks are mostly
+  // final pays two memory round trips per 64 units instead of one per unit).
+  // While one unit is swept, the next one's chunk extent, degrees and row
+  // states are in flight.  (The first batch's descriptors were requested
+  // before the LDS staging, so their latency overlaps it.)
+  for (int64_t b = 0; b < count; b += kC) {
+    if (b != 0) {
+      want = b + lane < count;
+      if (want) {
+        const Unit u = units[r0 + (b + lane) * step];
+        mine_c0 = u.c0;
+        mine_one = u.c1 == u.c0 + 1;
+      }
     }
-    if (want && skip_done && mine.c1 == mine.c0 + 1 && a.done[mine.c0] != 0) {
+    if (want && skip_done && mine_one && a.done[mine_c0] != 0) {
       want = false;
-      if (a.variant) S::skip_chunk(a, mine.c0);  // a push level may follow
+      if (a.variant) S::skip_chunk(a, mine_c0);  // a push level may follow
     }
     uint64_t todo = __ballot(want);
     // the next unit to sweep and its first chunk's metadata (loads in flight)
@@ -755,10 +774,12 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       if (!todo) return false;
       const int k = __ffsll((long long)todo) - 1;
       todo &= todo - 1;
-      nw.c0 = __builtin_amdgcn_readlane(mine.c0, k);
-      nw.c1 = __builtin_amdgcn_readlane(mine.c1, k);
-      nw.j0 = __builtin_amdgcn_readlane(mine.j0, k);
-      nw.j1 = __builtin_amdgcn_readlane(mine.j1, k);
+      // the same address in every lane: the descriptor is wave-uniform
+      const Unit u = units[r0 + (b + k) * step];
+      nw.c0 = __builtin_amdgcn_readfirstlane(u.c0);
+      nw.c1 = __builtin_amdgcn_readfirstlane(u.c1);
+      nw.j0 = __builtin_amdgcn_readfirstlane(u.j0);
+      nw.j1 = __builtin_amdgcn_readfirstlane(u.j1);
       n_len = a.cl[nw.c0];
       n_start = a.cs[nw.c0];
       n_dg = a.deg[nw.c0 * kC + lane];
@@ -815,12 +836,23 @@ __device__ __forceinline__ void level_body(const LevelArgs& a, const Unit* units
       } else {
         // SlimChunk: combine this piece, the last one to arrive post-processes.
         // Pieces exchange data only through device-scope atomics: each piece's
-        // combine has completed before its arrival is counted, so the last
+        // combine has completed before its arrival is counted, and a bundle
+        // is counted in the chunk only after all its pieces were, so the last
         // arrival's exchange sees every piece.
         if (acc != S::identity()) S::atomic_combine(a, row, acc);  // identity: no change
         wait_memory();
         int last = 0;
-        if (lane == 0) last = (atomicAdd(&a.arrive[c], 1) == npieces - 1);
+        if (lane == 0) {
+          const int32_t q = j0 / piece_cols;                   // piece index in the chunk
+          const int32_t nb = (npieces + kBundle - 1) / kBundle;  // bundles of the chunk
+          const int32_t bq = q / kBundle;
+          const int32_t bsize = min(kBundle, npieces - bq * kBundle);
+          int32_t* bc = arrive2 + bundle[c] + bq;
+          if (atomicAdd(bc, 1) == bsize - 1) {
+            atomicExch(bc, 0);  // every piece of the bundle has arrived: ready for the next level
+            last = (atomicAdd(&a.arrive[c], 1) == nb - 1);
+          }
+        }
         last = __shfl(last, 0);
         if (last) {
           acc = S::take(a, row);
@@ -848,7 +880,8 @@ __device__ __forceinline__ void level_entry(const LevelArgs& a, uint8_t* lds_sta
     }
     if (!prev_found) return;
   }
-  level_body<S, U, STAGED, VAL>(a, a.units, a.pieces, a.n_units, lds_stage);
+  level_body<S, U, STAGED, VAL>(a, a.units, a.pieces, a.n_units, a.bundle, a.arrive2,
+                                a.piece_cols, a.wave_off, lds_stage);
 }
 
 template <class S, int U, bool STAGED, bool VAL = false>
@@ -919,7 +952,8 @@ __global__ void persistent_kernel(LevelArgs a, void* buf_a, void* buf_b, int32_t
     a.vin = (k & 1) ? buf_a : buf_b;
     a.vout = (k & 1) ? buf_b : buf_a;
     a.count_stats = a.count_stats && (k <= status[2]);
-    level_body<S, U, STAGED>(a, a.units, a.pieces, a.n_units, lds_stage);
+    level_body<S, U, STAGED>(a, a.units, a.pieces, a.n_units, a.bundle, a.arrive2, a.piece_cols,
+                             nullptr, lds_stage);
     if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
     if (a.any[k % kRing] != level_tag(a.run_id, k)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = k;  // levels run
@@ -1100,6 +1134,7 @@ struct SchedArgs {
   double* sums;           // [0] discovered so far, [1] their degrees, [2] previous frontier size
   const float* model;     // nullptr = no model
   const float* anchors;   // the model's training domain [n_anchors][6], or nullptr
+  const float* box;       // [12] the anchors' box widened by tau: lower, then upper bounds
   int32_t n_anchors;
   float tau2;             // squared distance to the nearest anchor the model may answer at
   float* log;             // [log_cap * 12]
@@ -1113,6 +1148,8 @@ struct SchedArgs {
 // vertices discovered so far, [1] their degrees, [2] the previous frontier's
 // size.
 struct SchedShared {
+  float w[kModelSize];         // the model's parameters, staged once per level
+  float box[2 * kFeatures];    // the training domain's box (lower, upper)
   float x[kFeatures], h1[32], h2[32], out[kVariants];
   float near[64];  // per-thread nearest squared anchor distance (first 64 threads)
   unsigned long long cnt[kCountSlots][2];  // level k-1's found / frontier-degree slots
@@ -1129,6 +1166,14 @@ struct SchedShared {
 // workgroup, so all workgroups that call it with the same counters agree.
 __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh, bool writer) {
   const int t = threadIdx.x;
+  // The model (and its domain box) is staged into LDS by the whole
+  // workgroup in the same round of loads as the counters below, so scoring
+  // a level costs no global-memory round trip of its own.
+  const bool staged = (s.mode == 1) && s.model;
+  if (staged) {
+    for (int i = t; i < kModelSize; i += blockDim.x) sh.w[i] = s.model[i];
+    if (s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
+  }
   // Level k-1's counters: written by earlier kernels (or, in the persistent
   // form, before the grid barrier, whose acquire makes them visible), so
   // plain loads see them.  Sixteen lanes load one slot each, all in flight
@@ -1173,13 +1218,21 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     if (writer && t == 0) s.variant[k % kRing] = kStop;
     return kStop;
   }
-  // Learned: the MLP scores the four variants first.  Where its choice is
-  // the fixed heuristic's, that is the variant and the training domain needs
-  // no test; otherwise the level takes the model's choice only if its
-  // features lie within tau of an anchor of the training data.
-  const bool use_model = (s.mode == 1) && s.model;
+  // Learned: a level outside the box around the training domain is farther
+  // than tau from every anchor, so the heuristic decides without the model.
+  // Otherwise the MLP scores the four variants.  Where its choice is the
+  // fixed heuristic's, that is the variant and the anchors need no scan;
+  // otherwise the level takes the model's choice only if its features lie
+  // within tau of an anchor of the training data.
+  bool use_model = staged;
+  if (use_model && s.anchors && s.box) {
+    bool in = true;
+    for (int f = 0; f < kFeatures; ++f)
+      in = in && sh.x[f] >= sh.box[f] && sh.x[f] <= sh.box[kFeatures + f];
+    use_model = in;  // the same value in every thread
+  }
   if (use_model) {
-    const float* W1 = s.model;
+    const float* W1 = sh.w;
     const float* b1 = W1 + 32 * kFeatures;
     const float* W2 = b1 + 32;
     const float* b2 = W2 + 32 * 32;
@@ -1301,7 +1354,8 @@ __global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
   if (v == kStop) return;
   if (writer) sched_clear_level(s, k + 1);
   if (v < kPullVariants)
-    level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], lds_stage);
+    level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], a.vbundle[v],
+                             a.varrive2[v], a.vpiece_cols[v], nullptr, lds_stage);
   else
     push_scatter_body<S>(a, grid_wave(), grid_waves());
 }
@@ -1365,7 +1419,8 @@ __global__ void persistent_sched_kernel(LevelArgs a, SchedArgs s, void* buf_a, v
     }
     if (writer && k < cap) sched_clear_level(s, k + 1);
     if (v < kPullVariants) {
-      level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], lds_stage);
+      level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], a.vbundle[v],
+                             a.varrive2[v], a.vpiece_cols[v], nullptr, lds_stage);
     } else {
       push_scatter_body<S>(a, gw, nw);
       if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
@@ -1601,9 +1656,7 @@ static void launch_level_t(int waves, int unroll, unsigned grid, const LevelArgs
 int launch_level(int semiring, int waves, int unroll, int64_t max_groups, const LevelArgs& a,
                  void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int64_t groups = (a.n_units + waves - 1) / waves;
-  if (groups < 1) groups = 1;
-  if (max_groups > 0 && groups > max_groups) groups = max_groups;
+  const int64_t groups = level_groups(a.n_units, waves, max_groups);
   const unsigned grid = (unsigned)groups;
   switch (semiring) {
     case SS_TROPICAL: launch_level_t<Tropical>(waves, unroll, grid, a, st); break;
@@ -1648,6 +1701,7 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.sums = p.sums;
   s.model = p.model;
   s.anchors = p.anchors;
+  s.box = p.box;
   s.n_anchors = p.n_anchors;
   s.tau2 = p.tau2;
   s.log = p.log;

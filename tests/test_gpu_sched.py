@@ -85,7 +85,7 @@ def test_every_schedule_is_exact_and_features_match(ss, name):
     roots = graphgen.pick_roots(e, 2, seed=43)
     rng = np.random.default_rng(3)
     random_model = rng.normal(0, 0.5, mlp.PARAMS).astype(np.float32)
-    pull_v = 1  # the default split length (256) maps to the split-256 pull variant
+    pull_v = 1  # the default split length (at most 512) maps to the split-256 pull variant
     for root in roots:
         ex = oracle.expected(g, int(root))
         feats = mlp.features(ex.dist, g.degree, g.n, g.entries)
