@@ -91,7 +91,7 @@ static void release_graph(Graph* g) {
                   g->ws.rv,     g->ws.acc, g->ws.arrive, g->ws.done, g->ws.any, g->ws.counters,
                   g->d_voff,    g->bw.vis, g->bw.fa,   g->bw.fb,   g->bw.acc64,
                   g->bw.lvl,    g->bw.full, g->bw.root_rows, g->bw.slots,
-                  g->ws.q[0],   g->ws.q[1], g->ws.qn,   g->ws.variant, g->ws.ring_ctr,
+                  g->ws.q[0],   g->ws.q[1], g->ws.qn,   g->ws.variant, g->ws.decided, g->ws.ring_ctr,
                   g->ws.sched_sums, g->ws.model, g->ws.sched_log, g->ws.bar, g->ws.pstatus,
                   g->ws.segs,   g->ws.seg_n, g->ws.summ};
   for (void* p : ptrs)
@@ -154,17 +154,25 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
       ++i;
     }
   }
-  // Longest units first: a level hands units to its wavefronts round-robin,
-  // so this order spreads the long ones evenly over the grid (the greedy
-  // longest-first rule) and leaves the short ones to fill in.
+  // Longest units first, by powers of two: a level hands units to its
+  // wavefronts round-robin (or the per-wavefront assignment takes them in
+  // this order), so the long ones spread evenly over the grid and start
+  // first, and the short ones fill in.  Within one power of two the units
+  // keep chunk order, so neighbouring wavefronts work on neighbouring
+  // chunks (the pieces of one chunk stay together, and in a union of graphs
+  // a workgroup stays within one graph's vertices).
   auto cost = [&](const Unit& w) -> int64_t {
     if (w.c1 == w.c0 + 1) return (int64_t)w.j1 - w.j0;
     int64_t cols = 0;
     for (int32_t c = w.c0; c < w.c1; ++c) cols += g.h_cl[c];
     return cols;
   };
+  auto octave = [&](const Unit& w) -> int {
+    const int64_t c = cost(w);
+    return c > 0 ? 63 - __builtin_clzll((unsigned long long)c) : -1;
+  };
   std::stable_sort(units.begin(), units.end(),
-                   [&](const Unit& x, const Unit& y) { return cost(x) > cost(y); });
+                   [&](const Unit& x, const Unit& y) { return octave(x) > octave(y); });
   UnitList ul;
   ul.split_len = split;
   ul.pack_cols = pack;
@@ -306,6 +314,8 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.q[1], g.n_pad))) return rc;
   if ((rc = dalloc(&ws.qn, kRing))) return rc;
   if ((rc = dalloc(&ws.variant, kRing))) return rc;
+  if ((rc = dalloc(&ws.decided, kRing))) return rc;
+  SS_HIP(hipMemset(ws.decided, 0, sizeof(uint64_t) * kRing));
   if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kCountSlots * kCountFields))) return rc;
   if ((rc = dalloc(&ws.sched_sums, 8))) return rc;
   if ((rc = dalloc(&ws.model, kModelCap))) return rc;
@@ -630,6 +640,7 @@ static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
   sl.any = g.ws.any;
   sl.report = g.ws.d_report;
   sl.variant = g.ws.variant;
+  sl.decided = g.ws.decided;
   sl.qn = g.ws.qn;
   sl.seg_n = g.ws.seg_n;
   sl.ring_ctr = g.ws.ring_ctr;

@@ -108,6 +108,27 @@ extern "C" int slimsell_autotune(ss_graph* gp, const ss_autotune_opts* o, ss_aut
   ss_tune best = before;
   float best_ms = before_ms;
   int evaluated = 1;
+  // Coordinate descent stalls where two dimensions only pay together (no
+  // SlimChunk split pays only with one workgroup per unit and no LDS
+  // prefix on a union of small graphs), so it starts from the best of the
+  // current configuration and a few seeds that differ in several at once.
+  const ss_tune seeds[] = {
+      {0, 16, 8, 0, 0, 0},     // whole chunks, a wavefront per chunk, no prefix
+      {0, 4, 8, 0, 0, 0},      // the same in 4-wavefront workgroups
+      {256, 16, 8, 0, 0, 64},  // 256-column pieces, a wavefront per piece
+  };
+  for (const ss_tune& t : seeds) {
+    if (rc != SS_OK) break;
+    if (std::memcmp(&t, &best, sizeof(ss_tune)) == 0) continue;
+    float ms = 0.f;
+    rc = time_config(gp, *o, t, dist, parent, rv, &ms);
+    if (rc) break;
+    ++evaluated;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
   const std::vector<int32_t> splits = {0, 64, 128, 256, 512, 1024, 2048, 4096};
   const std::vector<int32_t> waves = {1, 2, 4, 8, 16};
   const std::vector<int32_t> unrolls = {4, 8, 16};

@@ -39,35 +39,6 @@ struct Stage {
   uint32_t summ = 0;
 };
 
-template <bool STAGED>
-__device__ __forceinline__ uint32_t gather_b32(Rsrc r, Stage st, uint32_t off) {
-  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-  const bool in = off < st.bytes;
-  uint32_t l = *reinterpret_cast<const uint32_t*>(st.lds + (in ? off : 0u));
-  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b32(r, in ? kOob : off, 0, 0);
-  return (in ? l : 0u) | g;
-}
-template <bool STAGED>
-__device__ __forceinline__ uint32_t gather_b8(Rsrc r, Stage st, uint32_t off) {
-  if (!STAGED) return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
-  const bool in = off < st.bytes;
-  const uint32_t l = st.lds[in ? off : 0u];
-  const uint32_t g = __builtin_amdgcn_raw_buffer_load_b8(r, in ? kOob : off, 0, 0);
-  return (in ? l : 0u) | g;
-}
-template <bool STAGED>
-__device__ __forceinline__ unsigned long long gather_b64(Rsrc r, Stage st, uint32_t off) {
-  unsigned long long l = 0ull;
-  bool in = false;
-  if (STAGED) {
-    in = off < st.bytes;
-    l = *reinterpret_cast<const unsigned long long*>(st.lds + (in ? off : 0u));
-  }
-  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, in ? kOob : off, 0, 0);
-  const unsigned long long g = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
-  return (in ? l : 0ull) | g;
-}
-
 // The product terms of one block of U columns: element c[t] of the gathered
 // vector for each lane (c[t] = -1 is padding).  KIND 0: one byte per row;
 // 1: four bytes per row; 2: the 32-bit word of a one-bit-per-row bitmap that
@@ -96,34 +67,52 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     // every term: LDS if the prefix holds it, else memory; both loads are
     // issued without a branch (the LDS address is clamped and its value
     // masked, the buffer load gets an out-of-range offset when LDS serves it)
+    uint32_t l[U], g[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
       const uint32_t off = row_offset<KIND>(c[t]);
       const bool in = STAGED && off < st.bytes;
-      uint32_t l = 0u;
+      l[t] = 0u;
       if (STAGED) {
         const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : 0u));
-        l = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
+        l[t] = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
       }
       const uint32_t o = in ? kOob : off;
-      y[t] = l | (byte_kind<KIND>() ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o, 0, 0)
-                                    : __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+      g[t] = byte_kind<KIND>() ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o, 0, 0)
+                               : __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+    }
+    // every load of the block is issued before the first use: without this
+    // fence a register-limited schedule waits for each load before issuing
+    // the next (and, waiting for all, for the next block's prefetch too)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      y[t] = l[t] | g[t];
       got[t] = c[t] >= 0;
     }
     return;
   }
   uint32_t o[U];  // memory offset of the term, kOob when LDS serves it or it is skipped
   bool some = false;
+  // one LDS read per term: the staged element if the prefix holds it, else
+  // the summary word of its chunk (all U reads in flight before the first use)
+  uint32_t lv[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const uint32_t cu = c[t] >= 0 ? (uint32_t)c[t] : 0u;
+    const uint32_t off = row_offset<KIND>(c[t]);
+    const bool in = off < st.bytes;
+    const uint32_t sw = st.summ + ((cu >> 11) << 2);
+    lv[t] = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const bool valid = c[t] >= 0;
     const uint32_t cu = valid ? (uint32_t)c[t] : 0u;
     const uint32_t off = row_offset<KIND>(c[t]);
     const bool in = off < st.bytes;
-    // one LDS read per term: the staged element if the prefix holds it,
-    // else the summary word of its chunk
-    const uint32_t sw = st.summ + ((cu >> 11) << 2);
-    const uint32_t v = *reinterpret_cast<const uint32_t*>(st.lds + (in ? (off & ~3u) : sw));
+    const uint32_t v = lv[t];
     y[t] = !in ? 0u : byte_kind<KIND>() ? (v >> ((off & 3u) * 8u)) & 0xFFu : v;
     const uint32_t need = (valid && !in ? 1u : 0u) & (v >> ((cu >> 6) & 31u));
     o[t] = need ? off : kOob;
@@ -137,6 +126,7 @@ __device__ __forceinline__ void gather_rows(Rsrc r, Stage st, const int32_t (&c)
     for (int t = 0; t < U; ++t)
       g[t] = byte_kind<KIND>() ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, o[t], 0, 0)
                                : __builtin_amdgcn_raw_buffer_load_b32(r, o[t], 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int t = 0; t < U; ++t) {
@@ -152,37 +142,60 @@ template <int U, bool STAGED>
 __device__ __forceinline__ void gather_masks(Rsrc r, Stage st, const int32_t (&c)[U],
                                              unsigned long long (&y)[U]) {
   if (!STAGED || !st.filter) {
+    unsigned long long l[U], g[U];
 #pragma unroll
-    for (int t = 0; t < U; ++t) y[t] = gather_b64<STAGED>(r, st, c[t] >= 0 ? (uint32_t)c[t] << 3 : kOob);
+    for (int t = 0; t < U; ++t) {
+      const uint32_t off = c[t] >= 0 ? (uint32_t)c[t] << 3 : kOob;
+      const bool in = STAGED && off < st.bytes;
+      l[t] = STAGED ? *reinterpret_cast<const unsigned long long*>(st.lds + (in ? off : 0u)) : 0ull;
+      if (!in) l[t] = 0ull;
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, in ? kOob : off, 0, 0);
+      g[t] = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load of the block in flight first
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] = l[t] | g[t];
     return;
   }
   uint32_t o[U];
   bool some = false;
+  // the staged mask, or (as its low word) the summary word of the chunk:
+  // all U LDS reads in flight before the first use
+  unsigned long long lv[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const uint32_t cu = c[t] >= 0 ? (uint32_t)c[t] : 0u;
+    const uint32_t off = c[t] >= 0 ? cu << 3 : kOob;
+    const uint32_t sw = st.summ + ((cu >> 11) << 2);
+    if (off < st.bytes) {
+      lv[t] = *reinterpret_cast<const unsigned long long*>(st.lds + off);
+    } else {
+      lv[t] = *reinterpret_cast<const uint32_t*>(st.lds + sw);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const bool valid = c[t] >= 0;
     const uint32_t cu = valid ? (uint32_t)c[t] : 0u;
     const uint32_t off = valid ? cu << 3 : kOob;
     const bool in = off < st.bytes;
-    // the staged mask, or (as its low word) the summary word of the chunk
-    const uint32_t sw = st.summ + ((cu >> 11) << 2);
-    unsigned long long v;
-    if (in) {
-      v = *reinterpret_cast<const unsigned long long*>(st.lds + off);
-    } else {
-      v = *reinterpret_cast<const uint32_t*>(st.lds + sw);
-    }
+    const unsigned long long v = lv[t];
     y[t] = in ? v : 0ull;
     const uint32_t need = (valid && !in ? 1u : 0u) & ((uint32_t)v >> ((cu >> 6) & 31u));
     o[t] = need ? off : kOob;
     some = some || need;
   }
   if (__any(some)) {
+    unsigned long long g[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
       const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, o[t], 0, 0);
-      y[t] |= ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
+      g[t] = ((unsigned long long)w[1] << 32) | (unsigned long long)w[0];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < U; ++t) y[t] |= g[t];
   }
 }
 

@@ -108,6 +108,7 @@ struct Workspace {
   int32_t* q[2] = {nullptr, nullptr};  // [n_pad] each, by level parity
   int32_t* qn = nullptr;               // [kRing] queue length per level
   int32_t* variant = nullptr;          // [kRing] chosen variant per level
+  uint64_t* decided = nullptr;         // [kRing] tagged decision per level (schedule kernel)
   unsigned long long* ring_ctr = nullptr;  // [kRing * kCountSlots * kCountFields]
   double* sched_sums = nullptr;        // [8] running totals for the features, 2 buffers
   float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
@@ -285,6 +286,7 @@ struct SchedLaunch {
   const float* model;
   const float* anchors;   // training-domain anchors [n_anchors][6] or nullptr
   const float* box;       // [12] their box widened by tau (lower, upper) or nullptr
+  uint64_t* decided;      // [kRing] decisions published for later workgroup rounds
   int32_t n_anchors;
   float tau2;             // squared distance beyond which the heuristic decides
   float* log;

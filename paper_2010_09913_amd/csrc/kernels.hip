@@ -279,6 +279,7 @@ struct SelMax {
 #pragma unroll
       for (int t = 0; t < U; ++t)
         x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit[t] ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);  // all U loads in flight before the first use
 #pragma unroll
       for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
     }
@@ -424,6 +425,7 @@ struct Dp {
 #pragma unroll
       for (int t = 0; t < U; ++t)
         x[t] = __builtin_amdgcn_raw_buffer_load_b32(rv, hit[t] ? (uint32_t)c[t] << 2 : kOob, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);  // all U loads in flight before the first use
 #pragma unroll
       for (int t = 0; t < U; ++t) acc = x[t] > acc ? x[t] : acc;
     }
@@ -1135,6 +1137,7 @@ struct SchedArgs {
   const float* model;     // nullptr = no model
   const float* anchors;   // the model's training domain [n_anchors][6], or nullptr
   const float* box;       // [12] the anchors' box widened by tau: lower, then upper bounds
+  uint64_t* decided;      // [kRing] published decisions (tag << 3 | variant + 2), or nullptr
   int32_t n_anchors;
   float tau2;             // squared distance to the nearest anchor the model may answer at
   float* log;             // [log_cap * 12]
@@ -1151,12 +1154,13 @@ struct SchedShared {
   float w[kModelSize];         // the model's parameters, staged once per level
   float box[2 * kFeatures];    // the training domain's box (lower, upper)
   float x[kFeatures], h1[32], h2[32], out[kVariants];
-  float near[64];  // per-thread nearest squared anchor distance (first 64 threads)
+  float near[16];  // per-wavefront nearest squared anchor distance
   unsigned long long cnt[kCountSlots][2];  // level k-1's found / frontier-degree slots
   double sums[3];
   float mf, mu;
   int32_t v, stop;
   int32_t need;  // model's choice + 1 when the training-domain test must decide, else 0
+  uint64_t pub;  // the level's published decision word, if any
 };
 
 // Level k's variant, from level k-1's counters, computed by a whole
@@ -1166,13 +1170,29 @@ struct SchedShared {
 // workgroup, so all workgroups that call it with the same counters agree.
 __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh, bool writer) {
   const int t = threadIdx.x;
+  const uint64_t tag = level_tag(s.run_id, k) & ((1ull << 61) - 1);
+  // A workgroup that starts after another one has decided this level (a
+  // later round of workgroups) takes the published decision.  Every
+  // workgroup reaches the same decision, so which one publishes does not
+  // matter (and any variant leaves the same BFS state).
+  if (t == 0)
+    sh.pub = (s.decided && !writer)
+                 ? __hip_atomic_load(&s.decided[k % kRing], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                 : 0ull;
   // The model (and its domain box) is staged into LDS by the whole
-  // workgroup in the same round of loads as the counters below, so scoring
-  // a level costs no global-memory round trip of its own.
+  // workgroup, and each thread holds one anchor of the training domain, in
+  // the same round of loads as the counters below, so scoring a level costs
+  // no global-memory round trip of its own.
   const bool staged = (s.mode == 1) && s.model;
+  float anc[kFeatures];
+  const bool has_anc = staged && s.anchors && t < s.n_anchors;
   if (staged) {
     for (int i = t; i < kModelSize; i += blockDim.x) sh.w[i] = s.model[i];
     if (s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
+    if (has_anc) {
+#pragma unroll
+      for (int f = 0; f < kFeatures; ++f) anc[f] = s.anchors[t * kFeatures + f];
+    }
   }
   // Level k-1's counters: written by earlier kernels (or, in the persistent
   // form, before the grid barrier, whose acquire makes them visible), so
@@ -1185,6 +1205,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     sh.cnt[t][1] = c[4];
   }
   __syncthreads();
+  if ((sh.pub >> 3) == tag) return (int32_t)(sh.pub & 7u) - 2;
   if (t == 0) {
     double nf = 0.0, mf = 0.0;
     for (int q = 0; q < kCountSlots; ++q) {
@@ -1216,6 +1237,9 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   __syncthreads();
   if (sh.stop) {
     if (writer && t == 0) s.variant[k % kRing] = kStop;
+    if (t == 0 && s.decided)
+      __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(kStop + 2),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return kStop;
   }
   // Learned: a level outside the box around the training domain is farther
@@ -1244,18 +1268,28 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       sh.h1[t] = acc > 0.f ? acc : 0.f;
     }
     __syncthreads();
-    if (t < 32) {
-      float acc = b2[t];
-      for (int j = 0; j < 32; ++j) acc += W2[t * 32 + j] * sh.h1[j];
-      sh.h2[t] = acc > 0.f ? acc : 0.f;
-    }
-    __syncthreads();
-    if (t < kVariants) {
-      float acc = b3[t];
-      for (int j = 0; j < 32; ++j) acc += W3[t * 32 + j] * sh.h2[j];
-      sh.out[t] = acc;
-    }
-    __syncthreads();
+    // layers 2 and 3: one thread per weight, each output the sum of a
+    // 32-lane group by a fixed butterfly (the same arithmetic whatever the
+    // workgroup size, so every form of the run decides alike); a weight row
+    // is contiguous in LDS, so the reads are free of bank conflicts
+    auto dense = [&](const float* W, const float* b, const float* in, float* out, int rows,
+                     bool relu) {
+      for (int base = 0; base < rows * 32; base += blockDim.x) {
+        const int i = base + t;
+        if (i < rows * 32) {
+          float p = W[i] * in[i & 31];
+#pragma unroll
+          for (int off = 16; off > 0; off >>= 1) p += __shfl_xor(p, off);
+          if ((i & 31) == 0) {
+            const float acc = b[i >> 5] + p;
+            out[i >> 5] = relu ? (acc > 0.f ? acc : 0.f) : acc;
+          }
+        }
+      }
+      __syncthreads();
+    };
+    dense(W2, b2, sh.h1, sh.h2, 32, true);
+    dense(W3, b3, sh.h2, sh.out, kVariants, false);
   }
   if (t == 0) {
     // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
@@ -1280,28 +1314,46 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   }
   __syncthreads();
   if (sh.need) {
-    // nearest anchor: threads 0..63 each scan a strided share, then a min
-    // tree (min is exact, so every workgroup gets the same value)
-    if (t < 64) {
-      float best = INFINITY;
-      for (int i = t; i < s.n_anchors; i += 64) {
-        float d2 = 0.f;
-        for (int f = 0; f < kFeatures; ++f) {
-          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
-          d2 = fmaf(df, df, d2);
-        }
-        best = d2 < best ? d2 : best;
+    // nearest anchor: each thread takes a strided share of the anchors (one
+    // each in a full workgroup, so their loads are all in flight at once),
+    // then a min over the wavefront and over the wavefronts (min is exact,
+    // so every workgroup gets the same value)
+    float best = INFINITY;
+    if (has_anc) {
+      float d2 = 0.f;
+#pragma unroll
+      for (int f = 0; f < kFeatures; ++f) {
+        const float df = sh.x[f] - anc[f];
+        d2 = fmaf(df, df, d2);
       }
-      sh.near[t] = best;
+      best = d2;
     }
+    for (int i = t + blockDim.x; i < s.n_anchors; i += blockDim.x) {  // small workgroups
+      float d2 = 0.f;
+#pragma unroll
+      for (int f = 0; f < kFeatures; ++f) {
+        const float df = sh.x[f] - s.anchors[i * kFeatures + f];
+        d2 = fmaf(df, df, d2);
+      }
+      best = d2 < best ? d2 : best;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float o = __shfl_xor(best, off);
+      best = o < best ? o : best;
+    }
+    if ((t & (kC - 1)) == 0) sh.near[t / kC] = best;
     __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-      if (t < w) sh.near[t] = sh.near[t + w] < sh.near[t] ? sh.near[t + w] : sh.near[t];
-      __syncthreads();
-    }
     // outside the training domain the heuristic's choice stands
-    if (t == 0 && sh.near[0] <= s.tau2) sh.v = sh.need - 1;
+    if (t == 0) {
+      float m = sh.near[0];
+      for (int w = 1; w < (int)(blockDim.x / kC); ++w) m = sh.near[w] < m ? sh.near[w] : m;
+      if (m <= s.tau2) sh.v = sh.need - 1;
+    }
   }
+  if (t == 0 && s.decided)
+    __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(sh.v + 2), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   if (t == 0 && writer) {
     const int32_t v = sh.v;
     s.variant[k % kRing] = v;
@@ -1702,6 +1754,7 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.model = p.model;
   s.anchors = p.anchors;
   s.box = p.box;
+  s.decided = p.decided;
   s.n_anchors = p.n_anchors;
   s.tau2 = p.tau2;
   s.log = p.log;
@@ -1798,6 +1851,7 @@ static int launch_persistent_u(int unroll, const LevelArgs& a, void* buf_a, void
   uint64_t limit = r.limit;
   if (r.sched) {
     SchedArgs sa = sched_args(*r.sched, 0, a.run_id);
+    sa.decided = nullptr;  // all workgroups are resident: each decides, and keeps its totals
     int32_t* q0 = r.q0;
     int32_t* q1 = r.q1;
     void* args[] = {&aa, &sa, &buf_a, &buf_b, &q0, &q1, &cap, &bar, &status, &limit};
