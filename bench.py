@@ -37,16 +37,16 @@ GATHER_BYTES = {"tropical": 4, "real": 4, "boolean": 1, "selmax": 4}
 
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-# profile summaries by kernel: (file base name, kernel-name substring in the
-# rocprofv3 trace, workload text)
+# profile summaries by kernel: (file base name, substrings that together name
+# the kernel in the rocprofv3 trace (every launch form of it), workload text)
 PROFILES = {
-    "level_kernel<selmax>": ("level_kernel_selmax_rmat_s22", "level_kernel<ss::SelMax",
+    "level_kernel<selmax>": ("level_kernel_selmax_rmat_s22", ("ss::level_kernel", "<ss::SelMax"),
                              "R-MAT s22, 64 roots, sel-max, sigma = n"),
-    "level_kernel<batch>": ("level_kernel_batch_rmat_s21", "level_kernel<ss::Batch",
+    "level_kernel<batch>": ("level_kernel_batch_rmat_s21", ("ss::level_kernel", "<ss::Batch"),
                             "R-MAT s21, 64 roots in one boolean SpMM, sigma = n"),
-    "level_kernel<dp>": ("level_kernel_dp_rmat_s22", "level_kernel<ss::Dp",
+    "level_kernel<dp>": ("level_kernel_dp_rmat_s22", ("ss::level_kernel", "<ss::Dp"),
                          "R-MAT s22, DP transformation after tropical BFS, 16 roots"),
-    "push_kernels<selmax>": ("push_kernels_selmax_rmat_s22", "push_",
+    "push_kernels<selmax>": ("push_kernels_selmax_rmat_s22", ("push_",),
                              "R-MAT s22, sel-max, forced push schedule, 16 roots"),
 }
 KERNEL_SOURCES = ["paper_2010_09913_amd/csrc/kernels.hip", "paper_2010_09913_amd/csrc/device.h",
@@ -78,6 +78,11 @@ def measured_traffic(kernel: str):
     return prof.get("traffic_bytes_per_launch")
 
 
+def named(name: str, parts) -> bool:
+    """Whether a kernel name contains every one of the given substrings."""
+    return all(p in name for p in parts)
+
+
 def _csv_rows(path):
     import csv
     with open(path) as f:
@@ -98,13 +103,13 @@ def profile_summary(args) -> int:
     kernel = args.kernel
     base, match, workload = PROFILES[kernel]
     stats = _csv_rows(_find(args.trace, "_kernel_stats.csv"))
-    rows = [r for r in stats if match in r["Name"]]
+    rows = [r for r in stats if named(r["Name"], match)]
     calls = sum(int(r["Calls"]) for r in rows)
     total_ns = sum(float(r["TotalDurationNs"]) for r in rows)
 
     def per_dispatch(d, counter, name_part):
         rr = [r for r in _csv_rows(_find(d, "_counter_collection.csv"))
-              if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+              if named(r["Kernel_Name"], name_part) and r["Counter_Name"] == counter]
         return sum(float(r["Counter_Value"]) for r in rr) / len(rr), len(rr)
 
     prof = {"kernel": kernel, "workload": workload, "source_hash": kernel_source_hash(),
@@ -113,8 +118,8 @@ def profile_summary(args) -> int:
     if args.fetch and args.write and args.copy_fetch and args.copy_write:
         fetch_kib, n_f = per_dispatch(args.fetch, "FETCH_SIZE", match)
         write_kib, n_w = per_dispatch(args.write, "WRITE_SIZE", match)
-        copy_f, _ = per_dispatch(args.copy_fetch, "FETCH_SIZE", "copyBuffer")
-        copy_w, _ = per_dispatch(args.copy_write, "WRITE_SIZE", "copyBuffer")
+        copy_f, _ = per_dispatch(args.copy_fetch, "FETCH_SIZE", ("copyBuffer",))
+        copy_w, _ = per_dispatch(args.copy_write, "WRITE_SIZE", ("copyBuffer",))
         gib_kib = float(1 << 20)                  # the copy reads and writes 1 GiB
         f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
         prof.update(fetch_kib_per_dispatch=fetch_kib, write_kib_per_dispatch=write_kib,
@@ -136,7 +141,7 @@ def profile_summary(args) -> int:
         lines.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                      f"{r['MinNs']} | {r['MaxNs']} | {float(r['Percentage']):.1f} |")
     lines += ["", f"{kernel}: {calls} calls, average {prof['avg_duration_ns']:.0f} ns "
-              f"(all instances matching `{match}`)."]
+              f"(all instances whose name contains {' and '.join('`' + m + '`' for m in match)})."]
     if "traffic_bytes_per_launch" in prof:
         lines += ["", "HBM counters per dispatch (KiB), and the copy probe (1 GiB read + 1 GiB "
                   "written per dispatch) that calibrates them:", "",
@@ -149,11 +154,68 @@ def profile_summary(args) -> int:
                   f"{prof['write_scale']:.3f} |", "",
                   f"Traffic per launch: {prof['traffic_bytes_per_launch'] / 1e6:.1f} MB "
                   f"(scaled fetch + write)."]
+    if args.pmc:
+        lines += pmc_summary(args, match, prof)
+        with open(os.path.join(args.out_dir, base + ".json"), "w") as f:
+            json.dump(prof, f, indent=1)
     lines += ["", f"Kernel sources hash {prof['source_hash']}.", ""]
     with open(os.path.join(args.out_dir, base + ".md"), "w") as f:
         f.write("\n".join(lines))
     print(json.dumps(prof))
     return 0
+
+
+def pmc_summary(args, match: str, prof: dict) -> list:
+    """Stall and cache counters of the kernel (one rocprofv3 --pmc pass per
+    directory), per dispatch, for all dispatches and for the long ones (the
+    levels that sweep most of the layout), with the ratios that explain where
+    the time goes."""
+    per = {}
+    for d in args.pmc:
+        for r in _csv_rows(_find(d, "_counter_collection.csv")):
+            if not named(r["Kernel_Name"], match):
+                continue
+            key = (d, int(r["Dispatch_Id"]))
+            e = per.setdefault(key, {"_ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    groups = {"all dispatches": list(per.values()),
+              "dispatches over 100 us": [e for e in per.values() if e["_ns"] > 100e3]}
+
+    def ratio(es, a, b):
+        num = sum(e.get(a, 0.0) for e in es)
+        den = sum(e.get(b, 0.0) for e in es)
+        return num / den if den else None
+
+    out = {}
+    lines = ["", "Stall and cache counters (`--pmc`, one pass per command):", ""]
+    lines += [f"    {c}" for c in args.cmd_pmc]
+    lines += ["", "| Ratio | " + " | ".join(groups) + " |", "|---|" + "---|" * len(groups)]
+    rows = [("wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES)", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES"),
+            ("cycles waiting on an instruction (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES)",
+             "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+            ("L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS))", "TCC_HIT_sum", None),
+            ("L1 to L2 read latency, cycles (TCP_TCC_READ_REQ_LATENCY / TCP_TCC_READ_REQ)",
+             "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum"),
+            ("L2 to memory read latency, cycles (TCC_EA0_RDREQ_LEVEL / TCC_EA0_RDREQ)",
+             "TCC_EA0_RDREQ_LEVEL_sum", "TCC_EA0_RDREQ_sum"),
+            ("L2 memory-read credit stalls per read request", "TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum",
+             "TCC_EA0_RDREQ_sum")]
+    for label, a, b in rows:
+        vals = []
+        for g, es in groups.items():
+            if b is None:
+                hit = sum(e.get("TCC_HIT_sum", 0.0) for e in es)
+                miss = sum(e.get("TCC_MISS_sum", 0.0) for e in es)
+                v = hit / (hit + miss) if hit + miss else None
+            else:
+                v = ratio(es, a, b)
+            vals.append(v)
+            out.setdefault(g, {})[label] = v
+        lines.append(f"| {label} | " + " | ".join("n/a" if v is None else f"{v:.3f}" for v in vals)
+                     + " |")
+    lines += ["", "Dispatches: " + ", ".join(f"{g} {len(es)}" for g, es in groups.items()) + "."]
+    prof["pmc"] = out
+    return lines
 
 
 def cpu_model() -> str:
@@ -597,6 +659,9 @@ def main() -> int:
     for name in ("trace", "fetch", "write", "copy-fetch", "copy-write"):
         ap.add_argument("--" + name, help="rocprofv3 output directory")
         ap.add_argument("--cmd-" + name, default="", help="the command that produced it")
+    ap.add_argument("--pmc", action="append", default=[],
+                    help="rocprofv3 --pmc output directory of stall/cache counters (repeatable)")
+    ap.add_argument("--cmd-pmc", action="append", default=[], help="the commands that produced them")
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"),
                     help="where --profile-summary writes")
     args = ap.parse_args()

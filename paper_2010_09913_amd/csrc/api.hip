@@ -13,9 +13,11 @@
 #include <cstring>
 #include <immintrin.h>
 #include <new>
+#include <numeric>
 #include <queue>
 #include <string>
 #include <thread>
+#include <tuple>
 
 #include "internal.h"
 
@@ -225,13 +227,31 @@ static int get_units(Graph& g, int32_t split, int32_t pack, UnitList** out,
 // long piece do.
 constexpr int64_t kUnitCost = 12;
 
-// The per-wavefront assignment of a unit list for a grid of W wavefronts:
-// units, longest first, each to the wavefront with the least work so far
-// (the longest-processing-time rule); ties go to the lower wavefront.
-static int get_assignment(UnitList& ul, int64_t W, const UnitList::Assignment** out,
-                          bool lookup_only) {
+// Relative streaming speed of wavefront w of a grid whose workgroups of 16
+// wavefronts run two per compute unit (n_cu compute units): a SIMD issues
+// the memory instructions of its older wavefronts first, so the workgroups
+// dispatched first, and inside a workgroup the wavefronts created first,
+// progress faster while all compete.  Measured per-wavefront end times of
+// full-sweep levels with equal work on MI355X (R-MAT s22) gave these
+// speeds, by dispatch round of the workgroup and the wavefront's rank on its
+// SIMD; the same pattern holds within a few percent on the sparser levels.
+static double slot_speed(int64_t w, int waves, int64_t n_cu) {
+  static const double kSpeed[2][4] = {{1.0, 0.98, 0.955, 0.925}, {0.88, 0.83, 0.78, 0.73}};
+  if (waves != 16 || n_cu <= 0) return 1.0;
+  const int64_t round = (w / waves) / n_cu;
+  const int rank = (int)(w % waves) / 4;
+  return round < 2 ? kSpeed[round][rank] : kSpeed[1][3];
+}
+
+// The per-wavefront assignment of a unit list for a grid of W wavefronts in
+// workgroups of `waves`: units, longest first, each to the wavefront that
+// would finish it first given its work so far and its speed (the
+// longest-processing-time rule for machines of different speeds).
+static int get_assignment(UnitList& ul, int64_t W, int waves, int64_t n_cu,
+                          const UnitList::Assignment** out, bool lookup_only) {
   *out = nullptr;
-  auto it = ul.assign.find(W);
+  const int64_t key = W * 32 + waves;
+  auto it = ul.assign.find(key);
   if (it != ul.assign.end()) {
     *out = &it->second;
     return SS_OK;
@@ -239,18 +259,43 @@ static int get_assignment(UnitList& ul, int64_t W, const UnitList::Assignment** 
   if (lookup_only || W < 1 || W > INT32_MAX) return SS_OK;  // round-robin instead
   const std::vector<Unit>& units = ul.h_units;
   const int64_t n = (int64_t)units.size();
+  // One heap of (work so far, tie order, wavefront) per speed class.  Ties
+  // are broken by a multiplicative permutation of the wavefronts, so that
+  // units of one kind (the long pieces come first) spread over the grid.
+  int64_t mult = (int64_t)(0.6180339887 * (double)W) | 1;
+  while (std::gcd(mult, W) != 1) mult += 2;
+  using Load = std::tuple<int64_t, int64_t, int64_t>;
+  using Heap = std::priority_queue<Load, std::vector<Load>, std::greater<Load>>;
+  std::vector<double> speeds;
+  std::vector<Heap> heaps;
+  for (int64_t w = 0; w < W; ++w) {
+    const double sp = slot_speed(w, waves, n_cu);
+    size_t c = 0;
+    while (c < speeds.size() && speeds[c] != sp) ++c;
+    if (c == speeds.size()) {
+      speeds.push_back(sp);
+      heaps.emplace_back();
+    }
+    heaps[c].push({0, (int64_t)(((__int128)w * mult) % W), w});
+  }
   std::vector<int32_t> owner((size_t)n);
-  using Load = std::pair<int64_t, int64_t>;  // (work so far, wavefront)
-  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-  for (int64_t w = 0; w < std::min<int64_t>(W, std::max<int64_t>(n, 1)); ++w) heap.push({0, w});
   std::vector<int64_t> per((size_t)W + 1, 0);
   for (int64_t i = 0; i < n; ++i) {
-    const int64_t cols = ul.h_cols[(size_t)i];
-    Load top = heap.top();
-    heap.pop();
-    owner[(size_t)i] = (int32_t)top.second;
-    ++per[(size_t)top.second + 1];
-    heap.push({top.first + cols + kUnitCost, top.second});
+    const int64_t cost = ul.h_cols[(size_t)i] + kUnitCost;
+    size_t best = 0;
+    double best_t = INFINITY;
+    for (size_t c = 0; c < heaps.size(); ++c) {
+      const double t = (double)(std::get<0>(heaps[c].top()) + cost) / speeds[c];
+      if (t < best_t) {
+        best_t = t;
+        best = c;
+      }
+    }
+    Load top = heaps[best].top();
+    heaps[best].pop();
+    owner[(size_t)i] = (int32_t)std::get<2>(top);
+    ++per[(size_t)std::get<2>(top) + 1];
+    heaps[best].push({std::get<0>(top) + cost, std::get<1>(top), std::get<2>(top)});
   }
   for (int64_t w = 0; w < W; ++w) per[(size_t)w + 1] += per[(size_t)w];
   std::vector<Unit> order((size_t)std::max<int64_t>(n, 1));
@@ -518,7 +563,9 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   {
     const int64_t W = level_groups(p->ul->count, p->waves, p->max_groups) * p->waves;
     // with no more units than wavefronts each takes one (or none): no table
-    if (W < p->ul->count && (rc = get_assignment(*p->ul, W, &p->as, no_alloc))) return rc;
+    if (W < p->ul->count &&
+        (rc = get_assignment(*p->ul, W, p->waves, g.n_cu, &p->as, no_alloc)))
+      return rc;
   }
   if (p->schedule) {
     const int32_t vsplit[kPullVariants] = {0, 256, 1024};
@@ -1097,6 +1144,10 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
       lds = 0;
     g->lds_cap = std::min(lds, 64 * 1024);
     g->lds_dev = lds;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess)
+      cus = 0;
+    g->n_cu = cus;  // 0: the unit assignment treats every wavefront alike
   }
   g->n = L->n;
   g->n_pad = L->n_pad;
@@ -1152,7 +1203,7 @@ int slimsell_build_from_layout(const ss_layout* L, void* stream, ss_graph** out)
     const UnitList::Assignment* as = nullptr;
     const int w = g->tune.waves_per_group;
     const int64_t W = level_groups(ul ? ul->count : 0, w, g->tune.max_groups) * w;
-    if (!rc && W < ul->count) rc = get_assignment(*ul, W, &as, false);
+    if (!rc && W < ul->count) rc = get_assignment(*ul, W, w, g->n_cu, &as, false);
   }
   if (!rc) rc = dalloc(&g->d_voff, 2);
   if (!rc && hipMemcpy(g->d_voff, g->h_voff.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice) !=
@@ -1212,7 +1263,7 @@ int slimsell_tune_set(ss_graph* g, const ss_tune* t) {
   const UnitList::Assignment* as = nullptr;
   if (!rc) {
     const int64_t W = level_groups(ul->count, w, t->max_groups) * w;
-    if (W < ul->count) rc = get_assignment(*ul, W, &as, false);
+    if (W < ul->count) rc = get_assignment(*ul, W, w, g->n_cu, &as, false);
   }
   return rc;
 }

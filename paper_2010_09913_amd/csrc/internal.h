@@ -171,6 +171,7 @@ constexpr int kRing = 1024;  // level tags / reports are kept in rings of this s
 
 struct Graph {
   int device = 0;
+  int64_t n_cu = 0;  // compute units of the device
   int32_t n = 0, n_pad = 0, sigma = 0;
   int64_t n_chunks = 0, entries = 0, cells = 0;
   int32_t max_cl = 0;

@@ -1145,6 +1145,7 @@ struct SchedArgs {
   int32_t mode;           // 1 learned, 2 heuristic, 3.. forced variant (mode - 3)
   int32_t heuristic_pull; // pull variant used by the heuristic
   double n, two_m;        // vertices, directed edges (2m)
+  float log2n, l2n, l2m;  // log2 n, log2 max(n, 2), log2(1 + max(2m, 1))
 };
 
 // Workgroup scratch of the schedule.  `sums` are the running totals: [0]
@@ -1153,15 +1154,19 @@ struct SchedArgs {
 struct SchedShared {
   float w[kModelSize];         // the model's parameters, staged once per level
   float box[2 * kFeatures];    // the training domain's box (lower, upper)
-  float x[kFeatures], h1[32], h2[32], out[kVariants];
+  float x[kFeatures], out[kVariants];
   float near[16];  // per-wavefront nearest squared anchor distance
   unsigned long long cnt[kCountSlots][2];  // level k-1's found / frontier-degree slots
   double sums[3];
   float mf, mu;
   int32_t v, stop;
-  int32_t need;  // model's choice + 1 when the training-domain test must decide, else 0
   uint64_t pub;  // the level's published decision word, if any
 };
+
+// Lane j's value of v, bit for bit (the builtin's value is an integer).
+__device__ __forceinline__ float lane_value(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
 
 // Level k's variant, from level k-1's counters, computed by a whole
 // workgroup (at least 32 threads; every thread must call it).  Advances
@@ -1187,7 +1192,13 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   float anc[kFeatures];
   const bool has_anc = staged && s.anchors && t < s.n_anchors;
   if (staged) {
-    for (int i = t; i < kModelSize; i += blockDim.x) sh.w[i] = s.model[i];
+    // (the second layer's weights transposed, so that lane u reading weight
+    // (u, j) of every hidden unit u at once touches consecutive words)
+    constexpr int kW2 = 32 * kFeatures + 32;
+    for (int i = t; i < kModelSize; i += blockDim.x) {
+      const int q = i - kW2;
+      sh.w[(q >= 0 && q < 32 * 32) ? kW2 + (q & 31) * 32 + (q >> 5) : i] = s.model[i];
+    }
     if (s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
     if (has_anc) {
 #pragma unroll
@@ -1217,37 +1228,36 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       sh.sums[0] += nf;
       sh.sums[1] += mf;
     }
-    const double mu = s.two_m - sh.sums[1];
-    const double l2n = log2(s.n > 2.0 ? s.n : 2.0), l2m = log2(1.0 + (s.two_m > 1.0 ? s.two_m : 1.0));
-    const double mu0 = mu > 0.0 ? mu : 0.0;
-    const double lnf = log2(1.0 + nf), lmf = log2(1.0 + mf), lmu = log2(1.0 + mu0);
-    const double fdeg = fmin(fmax((lmf - lnf) / 16.0, 0.0), 1.0);
-    const double udeg = fmin(fmax(log2((1.0 + mu0) / s.n) / 8.0, -1.0), 1.0);
-    const double ratio = fmin(fmax((lmf - lmu) / 16.0, -1.0), 1.0);
-    sh.x[0] = (float)(lnf / l2n);
-    sh.x[1] = (float)(lmf / l2m);
-    sh.x[2] = (float)(lmu / l2m);
-    sh.x[3] = (float)fdeg;
-    sh.x[4] = (float)udeg;
-    sh.x[5] = (float)ratio;
+    // counts and sums stay exact in double; the logarithms are taken in
+    // single precision (the features are single-precision values)
+    const double mu0 = fmax(s.two_m - sh.sums[1], 0.0);
+    const float lnf = log2f((float)(1.0 + nf)), lmf = log2f((float)(1.0 + mf));
+    const float lmu = log2f((float)(1.0 + mu0));
+    sh.x[0] = lnf / s.l2n;
+    sh.x[1] = lmf / s.l2m;
+    sh.x[2] = lmu / s.l2m;
+    sh.x[3] = fminf(fmaxf((lmf - lnf) / 16.0f, 0.0f), 1.0f);
+    sh.x[4] = fminf(fmaxf((lmu - s.log2n) / 8.0f, -1.0f), 1.0f);
+    sh.x[5] = fminf(fmaxf((lmf - lmu) / 16.0f, -1.0f), 1.0f);
     sh.sums[2] = nf;
     sh.mf = (float)mf;
     sh.mu = (float)mu0;
   }
   __syncthreads();
   if (sh.stop) {
-    if (writer && t == 0) s.variant[k % kRing] = kStop;
     if (t == 0 && s.decided)
       __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(kStop + 2),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (writer && t == 0) s.variant[k % kRing] = kStop;
     return kStop;
   }
   // Learned: a level outside the box around the training domain is farther
   // than tau from every anchor, so the heuristic decides without the model.
-  // Otherwise the MLP scores the four variants.  Where its choice is the
-  // fixed heuristic's, that is the variant and the anchors need no scan;
-  // otherwise the level takes the model's choice only if its features lie
-  // within tau of an anchor of the training data.
+  // Otherwise, at once: every thread measures its anchor's distance to the
+  // level's features (the nearest per wavefront goes to LDS), and the first
+  // wavefront scores the four variants with the MLP, one hidden unit per
+  // lane, in registers.  The level takes the model's choice where it is the
+  // heuristic's or the level lies within tau of an anchor.
   bool use_model = staged;
   if (use_model && s.anchors && s.box) {
     bool in = true;
@@ -1256,47 +1266,66 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     use_model = in;  // the same value in every thread
   }
   if (use_model) {
-    const float* W1 = sh.w;
-    const float* b1 = W1 + 32 * kFeatures;
-    const float* W2 = b1 + 32;
-    const float* b2 = W2 + 32 * 32;
-    const float* W3 = b2 + 32;
-    const float* b3 = W3 + kVariants * 32;
-    if (t < 32) {
-      float acc = b1[t];
-      for (int i = 0; i < kFeatures; ++i) acc += W1[t * kFeatures + i] * sh.x[i];
-      sh.h1[t] = acc > 0.f ? acc : 0.f;
-    }
-    __syncthreads();
-    // layers 2 and 3: one thread per weight, each output the sum of a
-    // 32-lane group by a fixed butterfly (the same arithmetic whatever the
-    // workgroup size, so every form of the run decides alike); a weight row
-    // is contiguous in LDS, so the reads are free of bank conflicts
-    auto dense = [&](const float* W, const float* b, const float* in, float* out, int rows,
-                     bool relu) {
-      for (int base = 0; base < rows * 32; base += blockDim.x) {
-        const int i = base + t;
-        if (i < rows * 32) {
-          float p = W[i] * in[i & 31];
+    if (s.anchors) {
+      float best = INFINITY;
+      if (has_anc) {
+        float d2 = 0.f;
 #pragma unroll
-          for (int off = 16; off > 0; off >>= 1) p += __shfl_xor(p, off);
-          if ((i & 31) == 0) {
-            const float acc = b[i >> 5] + p;
-            out[i >> 5] = relu ? (acc > 0.f ? acc : 0.f) : acc;
-          }
+        for (int f = 0; f < kFeatures; ++f) {
+          const float df = sh.x[f] - anc[f];
+          d2 = fmaf(df, df, d2);
         }
+        best = d2;
       }
-      __syncthreads();
-    };
-    dense(W2, b2, sh.h1, sh.h2, 32, true);
-    dense(W3, b3, sh.h2, sh.out, kVariants, false);
+      for (int i = t + blockDim.x; i < s.n_anchors; i += blockDim.x) {  // small workgroups
+        float d2 = 0.f;
+#pragma unroll
+        for (int f = 0; f < kFeatures; ++f) {
+          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
+          d2 = fmaf(df, df, d2);
+        }
+        best = d2 < best ? d2 : best;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+      }
+      if ((t & (kC - 1)) == 0) sh.near[t / kC] = best;  // min is exact: the same everywhere
+    }
+    if (t < kC) {
+      const float* W1 = sh.w;
+      const float* b1 = W1 + 32 * kFeatures;
+      const float* W2t = b1 + 32;  // [j][u]: transposed when staged
+      const float* b2 = W2t + 32 * 32;
+      const float* W3 = b2 + 32;
+      const float* b3 = W3 + kVariants * 32;
+      const int u = t & 31;  // hidden unit of this lane (lanes 32..63 mirror 0..31)
+      float h = b1[u];
+#pragma unroll
+      for (int i = 0; i < kFeatures; ++i) h = fmaf(W1[u * kFeatures + i], sh.x[i], h);
+      h = h > 0.f ? h : 0.f;
+      // layer 2: hidden unit u of layer 1 is read from lane u
+      float h2 = b2[u];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) h2 = fmaf(W2t[j * 32 + u], lane_value(h, j), h2);
+      h2 = h2 > 0.f ? h2 : 0.f;
+      // layer 3 in every lane (lane u scores variant u mod 4): a branch
+      // around it would let the compiler compute h2 only in the lanes that
+      // take the branch, while the readlanes read it from all 32
+      const int v3 = u & (kVariants - 1);
+      float o = b3[v3];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) o = fmaf(W3[v3 * 32 + j], lane_value(h2, j), o);
+      if (t < kVariants) sh.out[t] = o;
+    }
   }
+  __syncthreads();
   if (t == 0) {
     // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
     // pull once the frontier's edges exceed 1/14 of the unvisited edges
     const int32_t h = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
     int32_t v = h;
-    sh.need = 0;
     if (s.mode >= 3) {
       v = s.mode - 3;
     } else if (use_model) {
@@ -1306,56 +1335,25 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
         int32_t m = 0;
         for (int i = 1; i < kVariants; ++i)
           if (sh.out[i] < sh.out[m]) m = i;
-        if (m == h || !s.anchors) v = m;
-        else sh.need = m + 1;  // the domain test decides between m and h
+        bool near = !s.anchors;
+        if (!near) {
+          float d = sh.near[0];
+          for (int w = 1; w < (int)(blockDim.x / kC); ++w) d = sh.near[w] < d ? sh.near[w] : d;
+          near = d <= s.tau2;
+        }
+        // outside the training domain the heuristic's choice stands
+        if (m == h || near) v = m;
       }
     }
     sh.v = v;
   }
   __syncthreads();
-  if (sh.need) {
-    // nearest anchor: each thread takes a strided share of the anchors (one
-    // each in a full workgroup, so their loads are all in flight at once),
-    // then a min over the wavefront and over the wavefronts (min is exact,
-    // so every workgroup gets the same value)
-    float best = INFINITY;
-    if (has_anc) {
-      float d2 = 0.f;
-#pragma unroll
-      for (int f = 0; f < kFeatures; ++f) {
-        const float df = sh.x[f] - anc[f];
-        d2 = fmaf(df, df, d2);
-      }
-      best = d2;
-    }
-    for (int i = t + blockDim.x; i < s.n_anchors; i += blockDim.x) {  // small workgroups
-      float d2 = 0.f;
-#pragma unroll
-      for (int f = 0; f < kFeatures; ++f) {
-        const float df = sh.x[f] - s.anchors[i * kFeatures + f];
-        d2 = fmaf(df, df, d2);
-      }
-      best = d2 < best ? d2 : best;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float o = __shfl_xor(best, off);
-      best = o < best ? o : best;
-    }
-    if ((t & (kC - 1)) == 0) sh.near[t / kC] = best;
-    __syncthreads();
-    // outside the training domain the heuristic's choice stands
-    if (t == 0) {
-      float m = sh.near[0];
-      for (int w = 1; w < (int)(blockDim.x / kC); ++w) m = sh.near[w] < m ? sh.near[w] : m;
-      if (m <= s.tau2) sh.v = sh.need - 1;
-    }
-  }
+  const int32_t v = sh.v;
+  // the records go out after the last barrier, so no wavefront waits for them
   if (t == 0 && s.decided)
-    __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(sh.v + 2), __ATOMIC_RELAXED,
+    __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(v + 2), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   if (t == 0 && writer) {
-    const int32_t v = sh.v;
     s.variant[k % kRing] = v;
     if (s.log && k <= s.log_cap) {
       float* L = s.log + (int64_t)(k - 1) * 12;
@@ -1365,8 +1363,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       L[11] = (float)k;
     }
   }
-  __syncthreads();
-  return sh.v;
+  return v;
 }
 
 // Clear what level k accumulates into: its counters, queue length and push
@@ -1763,6 +1760,9 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.heuristic_pull = p.heuristic_pull;
   s.n = p.n;
   s.two_m = p.two_m;
+  s.log2n = (float)std::log2(p.n);
+  s.l2n = (float)std::log2(p.n > 2.0 ? p.n : 2.0);
+  s.l2m = (float)std::log2(1.0 + (p.two_m > 1.0 ? p.two_m : 1.0));
   return s;
 }
 
