@@ -457,8 +457,8 @@ int slimsell_sched_load(const float* weights, int64_t count);
 int slimsell_sched_clear(void);
 /* Per-level record of the last scheduled run on g: host float[cap][12] =
  * 6 features, 4 scores, chosen variant, level.  The scores are 0 without a
- * model and for a level outside the training domain's box (the anchors'
- * bounding box widened by tau), which the model does not score.  *levels
+ * model and for a level outside the model's training domain (farther than
+ * tau from every anchor), which the model does not score.  *levels
  * receives the records written: the last scheduled run's level count (its
  * iterations, at most min(n + 2, 65536)), clamped to cap; 0 before any
  * scheduled run. */

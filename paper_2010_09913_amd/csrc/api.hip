@@ -231,12 +231,13 @@ constexpr int64_t kUnitCost = 12;
 // wavefronts run two per compute unit (n_cu compute units): a SIMD issues
 // the memory instructions of its older wavefronts first, so the workgroups
 // dispatched first, and inside a workgroup the wavefronts created first,
-// progress faster while all compete.  Measured per-wavefront end times of
-// full-sweep levels with equal work on MI355X (R-MAT s22) gave these
-// speeds, by dispatch round of the workgroup and the wavefront's rank on its
-// SIMD; the same pattern holds within a few percent on the sparser levels.
+// progress faster while all compete.  Per-wavefront end times of the
+// full-sweep levels on MI355X (R-MAT s22), measured with equal work and then
+// again with the work weighted, gave these speeds, by dispatch round of the
+// workgroup and the wavefront's rank on its SIMD; the sparser levels follow
+// the same pattern.
 static double slot_speed(int64_t w, int waves, int64_t n_cu) {
-  static const double kSpeed[2][4] = {{1.0, 0.98, 0.955, 0.925}, {0.88, 0.83, 0.78, 0.73}};
+  static const double kSpeed[2][4] = {{1.0, 0.961, 0.930, 0.870}, {0.812, 0.729, 0.654, 0.580}};
   if (waves != 16 || n_cu <= 0) return 1.0;
   const int64_t round = (w / waves) / n_cu;
   const int rank = (int)(w % waves) / 4;
@@ -315,7 +316,7 @@ static int get_assignment(UnitList& ul, int64_t W, int waves, int64_t n_cu,
     if (as.d_off) (void)hipFree(as.d_off);
     return rc;
   }
-  *out = &ul.assign.emplace(W, as).first->second;
+  *out = &ul.assign.emplace(key, as).first->second;
   return SS_OK;
 }
 
@@ -453,6 +454,7 @@ struct RunPlan {
   UnitList* ul = nullptr;
   const UnitList::Assignment* as = nullptr;  // per-wavefront units of the level launch
   UnitList* vul[kPullVariants] = {nullptr, nullptr, nullptr};  // pull variants
+  const UnitList::Assignment* vas[kPullVariants] = {nullptr, nullptr, nullptr};
   bool has_model = false;
   int32_t n_anchors = 0;  // training-domain anchors carried by the model
   float tau = 0.f;
@@ -569,8 +571,18 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   }
   if (p->schedule) {
     const int32_t vsplit[kPullVariants] = {0, 256, 1024};
-    for (int v = 0; v < kPullVariants; ++v)
+    int64_t most = 0;
+    for (int v = 0; v < kPullVariants; ++v) {
       if ((rc = get_units(g, vsplit[v], 0, &p->vul[v]))) return rc;
+      most = std::max(most, p->vul[v]->count);
+    }
+    // the scheduled level's grid serves the variant with the most units;
+    // each variant's units get their assignment for that grid
+    const int64_t Ws = level_groups(most, p->waves, p->max_groups) * p->waves;
+    for (int v = 0; v < kPullVariants; ++v)
+      if (Ws < p->vul[v]->count &&
+          (rc = get_assignment(*p->vul[v], Ws, p->waves, g.n_cu, &p->vas[v], false)))
+        return rc;
     std::vector<float> host;
     uint64_t version = 0;
     p->has_model = (p->schedule == 1) && sched_model(&host, &version);
@@ -650,7 +662,8 @@ static LevelArgs base_args(Graph& g, const Workspace& ws, const RunPlan& p, cons
   if (p.schedule) {
     a.variant = g.ws.variant;
     for (int v = 0; v < kPullVariants; ++v) {
-      a.vunits[v] = p.vul[v]->d_units;
+      a.vunits[v] = p.vas[v] ? p.vas[v]->d_units : p.vul[v]->d_units;
+      a.vwave_off[v] = p.vas[v] ? p.vas[v]->d_off : nullptr;
       a.vpieces[v] = p.vul[v]->d_pieces;
       a.vn_units[v] = p.vul[v]->count;
       a.vbundle[v] = p.vul[v]->d_bundle;
@@ -1340,8 +1353,8 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
       unsigned long long* dpc =
           plan.counting ? g.ws.counters + plan.words_per_run * r + plan.lcap * kCountSlots * kCountFields
                         : nullptr;
-      if ((rc = launch_dp(g, g.ws, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
-                          parent_r, st, dpc, e0, e1)))
+      if ((rc = launch_dp(g, g.ws, *plan.ul, plan.as, plan.unroll, plan.waves, plan.max_groups,
+                          dist_r, parent_r, st, dpc, e0, e1)))
         return rc;
     }
     if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_last[r]))) return rc;
@@ -1364,8 +1377,12 @@ int slimsell_dp_parents(ss_graph* gp, const int32_t* dist, int32_t num_roots, in
   UnitList* ul = nullptr;
   int rc = get_units(g, split, pack, &ul);
   if (rc) return rc;
+  const int w = g.tune.waves_per_group;
+  const int64_t W = level_groups(ul->count, w, g.tune.max_groups) * w;
+  const UnitList::Assignment* as = nullptr;
+  if (W < ul->count && (rc = get_assignment(*ul, W, w, g.n_cu, &as, false))) return rc;
   for (int32_t r = 0; r < num_roots; ++r) {
-    rc = launch_dp(g, g.ws, *ul, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
+    rc = launch_dp(g, g.ws, *ul, as, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
                    dist + (int64_t)r * g.n, parent + (int64_t)r * g.n, st);
     if (rc) return rc;
   }
@@ -1548,8 +1565,8 @@ int slimsell_bfs_noalloc(ss_graph* gp, const int32_t* roots, int32_t num_roots, 
     rc = launch_finalise(s, g, w, dist_r, s == SS_SELMAX ? parent_r : nullptr,
                          real_val ? real_val + (int64_t)r * g.n : nullptr, st);
     if (rc) return rc;
-    if (dp && (rc = launch_dp(g, w, *plan.ul, plan.unroll, plan.waves, plan.max_groups, dist_r,
-                              parent_r, st)))
+    if (dp && (rc = launch_dp(g, w, *plan.ul, plan.as, plan.unroll, plan.waves, plan.max_groups,
+                              dist_r, parent_r, st)))
       return rc;
   }
   return SS_OK;

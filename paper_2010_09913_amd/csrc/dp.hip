@@ -57,8 +57,9 @@ __global__ void dp_finalise_kernel(int32_t n_pad, const int32_t* v, const int32_
   parent[o] = d == 0 ? o : ((d > 0 && b > 0) ? b - 1 : -1);
 }
 
-int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unroll, int waves,
-              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream,
+int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul,
+              const UnitList::Assignment* as, int unroll, int waves, int64_t max_groups,
+              const int32_t* dist, int32_t* parent, void* stream,
               unsigned long long* counters, void* ev_begin, void* ev_end) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t work = std::max<int64_t>(g.n_pad, g.n_chunks);
@@ -80,6 +81,10 @@ int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unrol
   a.bundle = ul.d_bundle;
   a.arrive2 = ul.d_arrive2;
   a.piece_cols = ul.split_len;
+  if (as) {
+    a.units = as->d_units;
+    a.wave_off = as->d_off;
+  }
   a.vin = ws.g;       // the codes
   a.state = ws.state; // best v per row
   a.d = ws.d;         // row distances

@@ -241,6 +241,7 @@ struct LevelArgs {
   // learned schedule / push variant (variant == nullptr: pull with `units`)
   const int32_t* variant;
   const Unit* vunits[kPullVariants];
+  const int32_t* vwave_off[kPullVariants];  // their per-wavefront ranges, or nullptr
   const int32_t* vpieces[kPullVariants];
   int64_t vn_units[kPullVariants];
   const int32_t* vbundle[kPullVariants];
@@ -331,8 +332,11 @@ int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
 // counter block, see LevelArgs::counters, written at level index 1) the sweep
 // counts its chunks and cells; ev_begin/ev_end (hipEvent_t or NULL) bracket
 // the sweep kernel.
-int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul, int unroll, int waves,
-              int64_t max_groups, const int32_t* dist, int32_t* parent, void* stream,
+// `as` (or NULL: round-robin) is the units' per-wavefront assignment for
+// the sweep's grid.
+int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul,
+              const UnitList::Assignment* as, int unroll, int waves, int64_t max_groups,
+              const int32_t* dist, int32_t* parent, void* stream,
               unsigned long long* counters = nullptr, void* ev_begin = nullptr,
               void* ev_end = nullptr);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);

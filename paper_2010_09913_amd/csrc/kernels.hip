@@ -1155,8 +1155,6 @@ struct SchedShared {
   float w[kModelSize];         // the model's parameters, staged once per level
   float box[2 * kFeatures];    // the training domain's box (lower, upper)
   float x[kFeatures], out[kVariants];
-  float near[16];  // per-wavefront nearest squared anchor distance
-  unsigned long long cnt[kCountSlots][2];  // level k-1's found / frontier-degree slots
   double sums[3];
   float mf, mu;
   int32_t v, stop;
@@ -1207,43 +1205,53 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   }
   // Level k-1's counters: written by earlier kernels (or, in the persistent
   // form, before the grid barrier, whose acquire makes them visible), so
-  // plain loads see them.  Sixteen lanes load one slot each, all in flight
-  // at once; the sums are formed in a fixed order, identically everywhere.
-  if (t < kCountSlots) {
-    const unsigned long long* c =
-        s.ring_ctr + ((int64_t)((k - 1) % kRing) * kCountSlots + t) * kCountFields;
-    sh.cnt[t][0] = c[0];
-    sh.cnt[t][1] = c[4];
+  // plain loads see them.  Sixteen lanes of the first wavefront load one
+  // slot each, all in flight at once, and add them up exactly (integers);
+  // its lane 0 forms the features.
+  if (t < kC) {
+    unsigned long long nf_u = 0ull, mf_u = 0ull;
+    if (t < kCountSlots) {
+      const unsigned long long* c =
+          s.ring_ctr + ((int64_t)((k - 1) % kRing) * kCountSlots + t) * kCountFields;
+      nf_u = c[0];
+      mf_u = c[4];
+    }
+#pragma unroll
+    for (int off = kCountSlots / 2; off > 0; off >>= 1) {
+      nf_u += __shfl_xor(nf_u, off);
+      mf_u += __shfl_xor(mf_u, off);
+    }
+    if (t == 0) {
+      const double nf = (double)nf_u, mf = (double)mf_u;
+      sh.stop = (k > 1 && nf_u == 0ull) ? 1 : 0;  // the previous level found nothing
+      if (k > 1) {
+        sh.sums[0] += nf;
+        sh.sums[1] += mf;
+      }
+      // the logarithms are taken in single precision (the features are
+      // single-precision values)
+      const double mu0 = fmax(s.two_m - sh.sums[1], 0.0);
+      const float lnf = log2f((float)(1.0 + nf)), lmf = log2f((float)(1.0 + mf));
+      const float lmu = log2f((float)(1.0 + mu0));
+      sh.x[0] = lnf / s.l2n;
+      sh.x[1] = lmf / s.l2m;
+      sh.x[2] = lmu / s.l2m;
+      sh.x[3] = fminf(fmaxf((lmf - lnf) / 16.0f, 0.0f), 1.0f);
+      sh.x[4] = fminf(fmaxf((lmu - s.log2n) / 8.0f, -1.0f), 1.0f);
+      sh.x[5] = fminf(fmaxf((lmf - lmu) / 16.0f, -1.0f), 1.0f);
+      sh.sums[2] = nf;
+      sh.mf = (float)mf;
+      sh.mu = (float)mu0;
+    }
+  }
+  // the anchors are needed in registers from here on: without this the
+  // compiler issues their loads only where they are used, after the barrier
+  if (has_anc) {
+#pragma unroll
+    for (int f = 0; f < kFeatures; ++f) asm volatile("" ::"v"(anc[f]));
   }
   __syncthreads();
   if ((sh.pub >> 3) == tag) return (int32_t)(sh.pub & 7u) - 2;
-  if (t == 0) {
-    double nf = 0.0, mf = 0.0;
-    for (int q = 0; q < kCountSlots; ++q) {
-      nf += (double)sh.cnt[q][0];
-      mf += (double)sh.cnt[q][1];
-    }
-    sh.stop = (k > 1 && nf == 0.0) ? 1 : 0;  // the previous level found nothing
-    if (k > 1) {
-      sh.sums[0] += nf;
-      sh.sums[1] += mf;
-    }
-    // counts and sums stay exact in double; the logarithms are taken in
-    // single precision (the features are single-precision values)
-    const double mu0 = fmax(s.two_m - sh.sums[1], 0.0);
-    const float lnf = log2f((float)(1.0 + nf)), lmf = log2f((float)(1.0 + mf));
-    const float lmu = log2f((float)(1.0 + mu0));
-    sh.x[0] = lnf / s.l2n;
-    sh.x[1] = lmf / s.l2m;
-    sh.x[2] = lmu / s.l2m;
-    sh.x[3] = fminf(fmaxf((lmf - lnf) / 16.0f, 0.0f), 1.0f);
-    sh.x[4] = fminf(fmaxf((lmu - s.log2n) / 8.0f, -1.0f), 1.0f);
-    sh.x[5] = fminf(fmaxf((lmf - lmu) / 16.0f, -1.0f), 1.0f);
-    sh.sums[2] = nf;
-    sh.mf = (float)mf;
-    sh.mu = (float)mu0;
-  }
-  __syncthreads();
   if (sh.stop) {
     if (t == 0 && s.decided)
       __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(kStop + 2),
@@ -1251,13 +1259,17 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     if (writer && t == 0) s.variant[k % kRing] = kStop;
     return kStop;
   }
-  // Learned: a level outside the box around the training domain is farther
-  // than tau from every anchor, so the heuristic decides without the model.
-  // Otherwise, at once: every thread measures its anchor's distance to the
-  // level's features (the nearest per wavefront goes to LDS), and the first
-  // wavefront scores the four variants with the MLP, one hidden unit per
-  // lane, in registers.  The level takes the model's choice where it is the
-  // heuristic's or the level lies within tau of an anchor.
+  // The fixed heuristic (the direction rule of Beamer et al. with alpha =
+  // 14): pull once the frontier's edges exceed 1/14 of the unvisited edges.
+  // Every thread evaluates it (and every workgroup alike).
+  const int32_t h = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
+  int32_t v = s.mode >= 3 ? s.mode - 3 : h;
+  // Learned: the model's choice stands only for a level inside its training
+  // domain (within tau of an anchor); outside it, the heuristic's.  A level
+  // outside the anchors' box widened by tau is outside for sure; otherwise
+  // every thread measures its anchor's distance to the level's features and
+  // the nearest decides.  Only then does the first wavefront score the four
+  // variants with the MLP, one hidden unit per lane, in registers.
   bool use_model = staged;
   if (use_model && s.anchors && s.box) {
     bool in = true;
@@ -1265,34 +1277,32 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       in = in && sh.x[f] >= sh.box[f] && sh.x[f] <= sh.box[kFeatures + f];
     use_model = in;  // the same value in every thread
   }
-  if (use_model) {
-    if (s.anchors) {
-      float best = INFINITY;
-      if (has_anc) {
-        float d2 = 0.f;
+  if (use_model && s.anchors) {
+    // inside the domain iff some anchor lies within tau: each thread tests
+    // its own (the comparison is exact, so every workgroup agrees), and one
+    // barrier ORs the answers
+    bool near = false;
+    if (has_anc) {
+      float d2 = 0.f;
 #pragma unroll
-        for (int f = 0; f < kFeatures; ++f) {
-          const float df = sh.x[f] - anc[f];
-          d2 = fmaf(df, df, d2);
-        }
-        best = d2;
+      for (int f = 0; f < kFeatures; ++f) {
+        const float df = sh.x[f] - anc[f];
+        d2 = fmaf(df, df, d2);
       }
-      for (int i = t + blockDim.x; i < s.n_anchors; i += blockDim.x) {  // small workgroups
-        float d2 = 0.f;
-#pragma unroll
-        for (int f = 0; f < kFeatures; ++f) {
-          const float df = sh.x[f] - s.anchors[i * kFeatures + f];
-          d2 = fmaf(df, df, d2);
-        }
-        best = d2 < best ? d2 : best;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const float o = __shfl_xor(best, off);
-        best = o < best ? o : best;
-      }
-      if ((t & (kC - 1)) == 0) sh.near[t / kC] = best;  // min is exact: the same everywhere
+      near = d2 <= s.tau2;
     }
+    for (int i = t + blockDim.x; i < s.n_anchors; i += blockDim.x) {  // small workgroups
+      float d2 = 0.f;
+#pragma unroll
+      for (int f = 0; f < kFeatures; ++f) {
+        const float df = sh.x[f] - s.anchors[i * kFeatures + f];
+        d2 = fmaf(df, df, d2);
+      }
+      near = near || d2 <= s.tau2;
+    }
+    use_model = __syncthreads_or(near ? 1 : 0) != 0;
+  }
+  if (use_model) {
     if (t < kC) {
       const float* W1 = sh.w;
       const float* b1 = W1 + 32 * kFeatures;
@@ -1301,14 +1311,14 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       const float* W3 = b2 + 32;
       const float* b3 = W3 + kVariants * 32;
       const int u = t & 31;  // hidden unit of this lane (lanes 32..63 mirror 0..31)
-      float h = b1[u];
+      float hh = b1[u];
 #pragma unroll
-      for (int i = 0; i < kFeatures; ++i) h = fmaf(W1[u * kFeatures + i], sh.x[i], h);
-      h = h > 0.f ? h : 0.f;
-      // layer 2: hidden unit u of layer 1 is read from lane u
+      for (int i = 0; i < kFeatures; ++i) hh = fmaf(W1[u * kFeatures + i], sh.x[i], hh);
+      hh = hh > 0.f ? hh : 0.f;
+      // layer 2: hidden unit j of layer 1 is read from lane j
       float h2 = b2[u];
 #pragma unroll
-      for (int j = 0; j < 32; ++j) h2 = fmaf(W2t[j * 32 + u], lane_value(h, j), h2);
+      for (int j = 0; j < 32; ++j) h2 = fmaf(W2t[j * 32 + u], lane_value(hh, j), h2);
       h2 = h2 > 0.f ? h2 : 0.f;
       // layer 3 in every lane (lane u scores variant u mod 4): a branch
       // around it would let the compiler compute h2 only in the lanes that
@@ -1318,38 +1328,23 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
 #pragma unroll
       for (int j = 0; j < 32; ++j) o = fmaf(W3[v3 * 32 + j], lane_value(h2, j), o);
       if (t < kVariants) sh.out[t] = o;
-    }
-  }
-  __syncthreads();
-  if (t == 0) {
-    // fixed heuristic (the direction rule of Beamer et al. with alpha = 14):
-    // pull once the frontier's edges exceed 1/14 of the unvisited edges
-    const int32_t h = (sh.mf * 14.0f > sh.mu) ? s.heuristic_pull : kPush;
-    int32_t v = h;
-    if (s.mode >= 3) {
-      v = s.mode - 3;
-    } else if (use_model) {
-      bool finite = true;
-      for (int i = 0; i < kVariants; ++i) finite = finite && isfinite(sh.out[i]);
-      if (finite) {
+      // lane 0: the lowest score, if every score is finite (else the heuristic)
+      const float o0 = lane_value(o, 0), o1 = lane_value(o, 1), o2 = lane_value(o, 2),
+                  o3 = lane_value(o, 3);
+      if (t == 0) {
         int32_t m = 0;
-        for (int i = 1; i < kVariants; ++i)
-          if (sh.out[i] < sh.out[m]) m = i;
-        bool near = !s.anchors;
-        if (!near) {
-          float d = sh.near[0];
-          for (int w = 1; w < (int)(blockDim.x / kC); ++w) d = sh.near[w] < d ? sh.near[w] : d;
-          near = d <= s.tau2;
-        }
-        // outside the training domain the heuristic's choice stands
-        if (m == h || near) v = m;
+        float om = o0;
+        if (o1 < om) { m = 1; om = o1; }
+        if (o2 < om) { m = 2; om = o2; }
+        if (o3 < om) { m = 3; om = o3; }
+        const bool finite = isfinite(o0) && isfinite(o1) && isfinite(o2) && isfinite(o3);
+        sh.v = finite ? m : h;
       }
     }
-    sh.v = v;
+    __syncthreads();
+    v = sh.v;
   }
-  __syncthreads();
-  const int32_t v = sh.v;
-  // the records go out after the last barrier, so no wavefront waits for them
+  // the records go out last, so no wavefront waits for them at a barrier
   if (t == 0 && s.decided)
     __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(v + 2), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1404,7 +1399,7 @@ __global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
   if (writer) sched_clear_level(s, k + 1);
   if (v < kPullVariants)
     level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], a.vbundle[v],
-                             a.varrive2[v], a.vpiece_cols[v], nullptr, lds_stage);
+                             a.varrive2[v], a.vpiece_cols[v], a.vwave_off[v], lds_stage);
   else
     push_scatter_body<S>(a, grid_wave(), grid_waves());
 }

@@ -286,3 +286,30 @@ def test_launch_configurations_give_identical_results(ss, tune):
     with pytest.raises(ss.SlimSellError):
         G.set_tune(unroll=3)
     G.close()
+
+
+def test_repeated_runs_reuse_the_prepared_work_lists(ss):
+    """Repeated BFS calls on one graph reuse the per-wavefront unit lists
+    (built once per graph, split length and grid): device memory stays flat
+    over many calls, and the results stay exact."""
+    import torch
+    e = graphgen.rmat(20, 16, seed=9)
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e, sigma=0)
+    root = int(graphgen.pick_roots(e, 1, seed=91)[0])
+    ex = oracle.expected(g, root)
+    try:
+        for _ in range(3):  # warm-up: work lists, workspace, torch's cache
+            G.bfs([root], "selmax")
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for _ in range(60):
+            res = G.bfs([root], "selmax")
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        note("free device memory", free0, "->", free1)
+        assert free0 - free1 < (4 << 20), (free0, free1)
+        np.testing.assert_array_equal(res.dist[0].cpu().numpy(), ex.dist)
+        np.testing.assert_array_equal(res.parent[0].cpu().numpy(), ex.parent)
+    finally:
+        G.close()
