@@ -1174,10 +1174,10 @@ __device__ __forceinline__ float lane_value(float v, int j) {
 __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh, bool writer) {
   const int t = threadIdx.x;
   const uint64_t tag = level_tag(s.run_id, k) & ((1ull << 61) - 1);
-  // A workgroup that starts after another one has decided this level (a
+  // A workgroup that starts after the writer has decided this level (a
   // later round of workgroups) takes the published decision.  Every
-  // workgroup reaches the same decision, so which one publishes does not
-  // matter (and any variant leaves the same BFS state).
+  // workgroup reaches the same decision (and any variant leaves the same
+  // BFS state).
   if (t == 0)
     sh.pub = (s.decided && !writer)
                  ? __hip_atomic_load(&s.decided[k % kRing], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -1253,7 +1253,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   __syncthreads();
   if ((sh.pub >> 3) == tag) return (int32_t)(sh.pub & 7u) - 2;
   if (sh.stop) {
-    if (t == 0 && s.decided)
+    if (writer && t == 0 && s.decided)
       __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(kStop + 2),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (writer && t == 0) s.variant[k % kRing] = kStop;
@@ -1344,8 +1344,10 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     __syncthreads();
     v = sh.v;
   }
-  // the records go out last, so no wavefront waits for them at a barrier
-  if (t == 0 && s.decided)
+  // the records go out last, so no wavefront waits for them at a barrier;
+  // only the writer publishes (stores from every workgroup to one word are
+  // serialised by the memory system, about 57 ns each)
+  if (writer && t == 0 && s.decided)
     __hip_atomic_store(&s.decided[k % kRing], (tag << 3) | (uint64_t)(v + 2), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   if (t == 0 && writer) {
