@@ -362,7 +362,7 @@ static int alloc_workspace(Graph& g) {
   if ((rc = dalloc(&ws.variant, kRing))) return rc;
   if ((rc = dalloc(&ws.decided, kRing))) return rc;
   SS_HIP(hipMemset(ws.decided, 0, sizeof(uint64_t) * kRing));
-  if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kCountSlots * kCountFields))) return rc;
+  if ((rc = dalloc(&ws.ring_ctr, (int64_t)kRing * kRingSlots * kCountFields))) return rc;
   if ((rc = dalloc(&ws.sched_sums, 8))) return rc;
   if ((rc = dalloc(&ws.model, kModelCap))) return rc;
   ws.sched_log_cap = std::min<int64_t>((int64_t)g.n + 2, 65536);

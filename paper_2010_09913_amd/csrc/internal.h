@@ -109,7 +109,7 @@ struct Workspace {
   int32_t* qn = nullptr;               // [kRing] queue length per level
   int32_t* variant = nullptr;          // [kRing] chosen variant per level
   uint64_t* decided = nullptr;         // [kRing] tagged decision per level (schedule kernel)
-  unsigned long long* ring_ctr = nullptr;  // [kRing * kCountSlots * kCountFields]
+  unsigned long long* ring_ctr = nullptr;  // [kRing * kRingSlots * kCountFields]
   double* sched_sums = nullptr;        // [8] running totals for the features, 2 buffers
   float* sched_log = nullptr;          // [sched_log_cap * 12] features, scores, variant
   int64_t sched_log_cap = 0;
@@ -149,7 +149,12 @@ struct BatchWorkspace {
   int64_t root_cap = 0;
 };
 
-constexpr int kCountSlots = 16;  // counter atomics are spread over this many slots
+constexpr int kCountSlots = 16;  // statistics counter atomics are spread over this many slots
+// The schedule's counters (read on the critical path of every scheduled
+// level) are spread wider: one slot per lane of a wavefront, so a level's
+// workgroups meet at most a few to an address (atomics on one address from
+// all XCDs are serialised by the memory system).
+constexpr int kRingSlots = 64;
 // counter fields: discovered, active chunks, active cells, max active cl,
 // degree sum of the discovered rows (frontier edges of the next level)
 constexpr int kCountFields = 5;

@@ -619,11 +619,11 @@ __device__ __forceinline__ void flush_counters(const LevelArgs& a, int lane, uin
   if (t[0]) a.any[a.level % kRing] = level_tag(a.run_id, a.level);
   if (!(t[0] | t[1] | t[2] | t[4])) return;
   unsigned long long* dst[2] = {nullptr, nullptr};
-  const int slot = blockIdx.x % kCountSlots;
   if (a.count_stats)
-    dst[0] = a.counters + ((int64_t)a.level * kCountSlots + slot) * kCountFields;
+    dst[0] = a.counters + ((int64_t)a.level * kCountSlots + blockIdx.x % kCountSlots) * kCountFields;
   if (a.ring_ctr)
-    dst[1] = a.ring_ctr + ((int64_t)(a.level % kRing) * kCountSlots + slot) * kCountFields;
+    dst[1] = a.ring_ctr +
+             ((int64_t)(a.level % kRing) * kRingSlots + blockIdx.x % kRingSlots) * kCountFields;
   for (unsigned long long* ctr : dst) {
     if (!ctr) continue;
     if (t[0]) atomicAdd(&ctr[0], t[0]);
@@ -976,18 +976,70 @@ __global__ void persistent_kernel(LevelArgs a, void* buf_a, void* buf_b, int32_t
 
 constexpr int kPushSegment = 1024;  // longer rows are cut into segments of this many cells
 
+// Rows claimed by a workgroup are staged in LDS and appended to the level's
+// queue with one atomic per workgroup at the end of the phase (an atomic
+// per wavefront and column on the one queue counter, from every XCD, is
+// serialised by the memory system, about 57 ns each).  A batch that does
+// not fit goes to the queue directly.  `cut` is where the first such batch
+// began: the staged rows are exactly [0, min(n, cut)).
+constexpr int kPushStage = 2048;
+struct PushStage {
+  int32_t n, cut, base;
+  int32_t rows[kPushStage];
+};
+
+// A push phase inside a kernel that also runs pull levels stages its rows
+// in the LDS of the prefix (not in use on a push level), if it is large
+// enough: a static buffer would cost the pull levels occupancy.
+template <bool STAGED>
+__device__ __forceinline__ PushStage* push_stage(const LevelArgs& a, uint8_t* lds_stage) {
+  return (STAGED && a.lds_bytes >= sizeof(PushStage)) ? reinterpret_cast<PushStage*>(lds_stage)
+                                                     : nullptr;
+}
+
+// Every thread of the workgroup calls these (ps == nullptr: no staging).
+__device__ __forceinline__ void stage_begin(PushStage* ps) {
+  if (!ps) return;
+  if (threadIdx.x == 0) {
+    ps->n = 0;
+    ps->cut = kPushStage;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void stage_flush(const LevelArgs& a, PushStage* ps) {
+  if (!ps) return;
+  __syncthreads();
+  const int32_t cnt = ps->n < ps->cut ? ps->n : ps->cut;
+  if (threadIdx.x == 0 && cnt > 0) ps->base = atomicAdd(&a.qn[a.level % kRing], cnt);
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < cnt; i += blockDim.x) a.q_out[ps->base + i] = ps->rows[i];
+}
+
 template <class S>
 __device__ __forceinline__ void push_one(const LevelArgs& a, int32_t w, typename S::Acc val,
-                                         int lane) {
+                                         int lane, PushStage* ps) {
   bool claimed = false;
   if (w >= 0 && S::live(a, w)) claimed = S::claim(a, w, val);
   const uint64_t m = __ballot(claimed);
   if (!m) return;
   const int leader = __ffsll((long long)m) - 1;
-  int32_t base = 0;
-  if (lane == leader) base = atomicAdd(&a.qn[a.level % kRing], (int32_t)__popcll(m));
+  const int32_t cnt = (int32_t)__popcll(m);
+  int32_t slot = 0, base = -1;
+  if (lane == leader) {
+    if (ps) slot = atomicAdd(&ps->n, cnt);
+    if (!ps || slot + cnt > kPushStage) {
+      if (ps && slot < kPushStage) ps->cut = slot;  // the one batch that crosses the end
+      base = atomicAdd(&a.qn[a.level % kRing], cnt);
+    }
+  }
+  slot = __shfl(slot, leader);
   base = __shfl(base, leader);
-  if (claimed) a.q_out[base + __popcll(m & lanes_below(lane))] = w;
+  const int32_t r = __popcll(m & lanes_below(lane));
+  if (claimed) {
+    if (base < 0) ps->rows[slot + r] = w;
+    else a.q_out[base + r] = w;
+  }
 }
 
 // Short frontier rows: one lane each.  Long rows are cut into segments of
@@ -1002,8 +1054,10 @@ __device__ __forceinline__ int32_t load_count(const int32_t* p) {
 // k-1 (or the scheduled run's init) filled, or, after a pull level, which
 // keeps no queue, from a scan of the rows that entered at level k-1.
 template <class S>
-__device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw, int64_t nw) {
+__device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw, int64_t nw,
+                                                  PushStage* ps) {
   const int lane = threadIdx.x & (kC - 1);
+  stage_begin(ps);
   const bool scan = a.level > 1 && a.variant[(a.level - 1) % kRing] < kPullVariants &&
                     a.variant[(a.level - 1) % kRing] >= 0;
   const int64_t nq = scan ? (int64_t)a.n_pad : (int64_t)load_count(&a.qn[(a.level - 1) % kRing]);
@@ -1028,7 +1082,7 @@ __device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw
     if (u >= 0 && !big) {
       const int32_t* p = a.col + a.cs[u >> 6] + (u & 63);
       const typename S::Acc val = S::push_value(a, u);
-      for (int32_t j = 0; j < du; ++j) push_one<S>(a, p[(int64_t)j * kC], val, lane);
+      for (int32_t j = 0; j < du; ++j) push_one<S>(a, p[(int64_t)j * kC], val, lane, ps);
       cells += (uint64_t)du;
     }
     // long rows: reserve their segments with one atomic per wavefront
@@ -1049,13 +1103,16 @@ __device__ __forceinline__ void push_scatter_body(const LevelArgs& a, int64_t gw
         a.segs[start + excl + q] = make_int2(u, q * kPushSegment);
     }
   }
+  stage_flush(a, ps);
   flush_counters(a, lane, 0, 0, wave_sum64(cells), 0, 0);
 }
 
 // Long frontier rows, one segment of kPushSegment cells per wavefront pass.
 template <class S>
-__device__ __forceinline__ void push_segments_body(const LevelArgs& a, int64_t gw, int64_t nw) {
+__device__ __forceinline__ void push_segments_body(const LevelArgs& a, int64_t gw, int64_t nw,
+                                                   PushStage* ps) {
   const int lane = threadIdx.x & (kC - 1);
+  stage_begin(ps);
   const int32_t ns = load_count(a.seg_n);
   uint64_t cells = 0;
   for (int64_t s = gw; s < ns; s += nw) {
@@ -1066,9 +1123,10 @@ __device__ __forceinline__ void push_segments_body(const LevelArgs& a, int64_t g
     const int32_t* p = a.col + a.cs[u >> 6] + (u & 63);
     const typename S::Acc val = S::push_value(a, u);
     for (int32_t j = j0 + lane; j - lane < j1; j += kC)
-      push_one<S>(a, j < j1 ? p[(int64_t)j * kC] : -1, val, lane);
+      push_one<S>(a, j < j1 ? p[(int64_t)j * kC] : -1, val, lane, ps);
     cells += (uint64_t)(j1 - j0);
   }
+  stage_flush(a, ps);
   flush_counters(a, lane, 0, 0, lane == 0 ? cells : 0, 0, 0);
 }
 
@@ -1106,7 +1164,8 @@ __device__ __forceinline__ int64_t grid_waves() { return ((int64_t)gridDim.x * b
 template <class S>
 __global__ void push_segments_kernel(LevelArgs a) {
   if (a.variant[a.level % kRing] != kPush) return;
-  push_segments_body<S>(a, grid_wave(), grid_waves());
+  __shared__ PushStage ps;
+  push_segments_body<S>(a, grid_wave(), grid_waves(), &ps);
 }
 
 template <class S>
@@ -1205,19 +1264,19 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   }
   // Level k-1's counters: written by earlier kernels (or, in the persistent
   // form, before the grid barrier, whose acquire makes them visible), so
-  // plain loads see them.  Sixteen lanes of the first wavefront load one
-  // slot each, all in flight at once, and add them up exactly (integers);
-  // its lane 0 forms the features.
+  // plain loads see them.  The lanes of the first wavefront load one slot
+  // each, all in flight at once, and add them up exactly (integers); its
+  // lane 0 forms the features.
   if (t < kC) {
     unsigned long long nf_u = 0ull, mf_u = 0ull;
-    if (t < kCountSlots) {
+    if (t < kRingSlots) {
       const unsigned long long* c =
-          s.ring_ctr + ((int64_t)((k - 1) % kRing) * kCountSlots + t) * kCountFields;
+          s.ring_ctr + ((int64_t)((k - 1) % kRing) * kRingSlots + t) * kCountFields;
       nf_u = c[0];
       mf_u = c[4];
     }
 #pragma unroll
-    for (int off = kCountSlots / 2; off > 0; off >>= 1) {
+    for (int off = kRingSlots / 2; off > 0; off >>= 1) {
       nf_u += __shfl_xor(nf_u, off);
       mf_u += __shfl_xor(mf_u, off);
     }
@@ -1366,8 +1425,8 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
 // Clear what level k accumulates into: its counters, queue length and push
 // segment count (one workgroup).
 __device__ __forceinline__ void sched_clear_level(const SchedArgs& s, int32_t k) {
-  unsigned long long* mine = s.ring_ctr + (int64_t)(k % kRing) * kCountSlots * kCountFields;
-  for (int i = threadIdx.x; i < kCountSlots * kCountFields; i += blockDim.x) mine[i] = 0ull;
+  unsigned long long* mine = s.ring_ctr + (int64_t)(k % kRing) * kRingSlots * kCountFields;
+  for (int i = threadIdx.x; i < kRingSlots * kCountFields; i += blockDim.x) mine[i] = 0ull;
   if (threadIdx.x == 0) {
     s.qn[k % kRing] = 0;
     s.seg_n[k & 1] = 0;
@@ -1403,7 +1462,7 @@ __global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
     level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], a.vbundle[v],
                              a.varrive2[v], a.vpiece_cols[v], a.vwave_off[v], lds_stage);
   else
-    push_scatter_body<S>(a, grid_wave(), grid_waves());
+    push_scatter_body<S>(a, grid_wave(), grid_waves(), push_stage<STAGED>(a, lds_stage));
 }
 
 // Level-0 state of a scheduled run: the root is the frontier queue, and the
@@ -1413,7 +1472,7 @@ __global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
 __global__ void sched_init_kernel(int32_t root_row, const int32_t* deg, int32_t* q0, int32_t* qn,
                                   int32_t* seg_n, unsigned long long* ring_ctr, double* sums) {
   const int t = threadIdx.x;
-  for (int i = t; i < 2 * kCountSlots * kCountFields; i += blockDim.x) ring_ctr[i] = 0ull;
+  for (int i = t; i < 2 * kRingSlots * kCountFields; i += blockDim.x) ring_ctr[i] = 0ull;
   __syncthreads();
   if (t == 0) {
     const int32_t d = deg[root_row];
@@ -1468,10 +1527,10 @@ __global__ void persistent_sched_kernel(LevelArgs a, SchedArgs s, void* buf_a, v
       level_body<S, U, STAGED>(a, a.vunits[v], a.vpieces[v], a.vn_units[v], a.vbundle[v],
                              a.varrive2[v], a.vpiece_cols[v], nullptr, lds_stage);
     } else {
-      push_scatter_body<S>(a, gw, nw);
+      push_scatter_body<S>(a, gw, nw, push_stage<STAGED>(a, lds_stage));
       if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
       if (load_count(a.seg_n) > 0) {
-        push_segments_body<S>(a, gw, nw);
+        push_segments_body<S>(a, gw, nw, push_stage<STAGED>(a, lds_stage));
         if (!grid_barrier(bar, gridDim.x, limit, &status[1])) return;
       }
       push_post_body<S>(a, gw, nw);
