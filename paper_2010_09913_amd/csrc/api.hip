@@ -233,11 +233,11 @@ constexpr int64_t kUnitCost = 12;
 // dispatched first, and inside a workgroup the wavefronts created first,
 // progress faster while all compete.  Per-wavefront end times of the
 // full-sweep levels on MI355X (R-MAT s22), measured with equal work and then
-// again with the work weighted, gave these speeds, by dispatch round of the
+// twice again with the work weighted, gave these speeds, by dispatch round of the
 // workgroup and the wavefront's rank on its SIMD; the sparser levels follow
 // the same pattern.
 static double slot_speed(int64_t w, int waves, int64_t n_cu) {
-  static const double kSpeed[2][4] = {{1.0, 0.961, 0.930, 0.870}, {0.812, 0.729, 0.654, 0.580}};
+  static const double kSpeed[2][4] = {{1.0, 0.964, 0.925, 0.866}, {0.80, 0.702, 0.609, 0.516}};
   if (waves != 16 || n_cu <= 0) return 1.0;
   const int64_t round = (w / waves) / n_cu;
   const int rank = (int)(w % waves) / 4;
