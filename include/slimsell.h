@@ -132,6 +132,11 @@ int slimsell_build(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
  *   n_per_graph    : host int32[num_graphs], each >= 1.
  *   C, sigma       : as slimsell_layout_build, applied to every graph
  *                    (sigma 0 = sort all rows of that graph).
+ * A union of two or more graphs starts with the launch configuration
+ * {split_len 128, waves_per_group 8, unroll 8, max_groups 0, pack_cols 0,
+ * lds_kib 0} (one wavefront per work unit, balanced by the dispatcher),
+ * not the single-graph default; slimsell_tune_set or slimsell_autotune
+ * replace it.
  * Errors: as slimsell_build; the union must have fewer than 2^31 rows.
  */
 int slimsell_build_multi(int32_t num_graphs, const int64_t* edge_offsets, const int32_t* src,
