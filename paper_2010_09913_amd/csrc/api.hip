@@ -1336,11 +1336,15 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
     if (o->iterations_out) o->iterations_out[r] = log.iters[r];
     int32_t* dist_r = dist + (int64_t)r * g.n;
     int32_t* parent_r = parent ? parent + (int64_t)r * g.n : nullptr;
-    rc = launch_finalise(s, g, g.ws, dist_r, s == SS_SELMAX ? parent_r : nullptr,
-                         real_val ? real_val + (int64_t)r * g.n : nullptr, st);
-    if (rc) return rc;
-    // the other semirings get parents by the DP transformation (Section II-C)
-    if (parent_r && s != SS_SELMAX) {
+    // the other semirings get parents by the DP transformation (Section II-C),
+    // whose last pass also writes the distances unless real values are wanted
+    const bool dp = parent_r && s != SS_SELMAX;
+    if (!dp || real_val) {
+      rc = launch_finalise(s, g, g.ws, dist_r, s == SS_SELMAX ? parent_r : nullptr,
+                           real_val ? real_val + (int64_t)r * g.n : nullptr, st);
+      if (rc) return rc;
+    }
+    if (dp) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       log.dp[r] = 1;
       if (plan.timing) {
@@ -1353,8 +1357,9 @@ int slimsell_bfs(ss_graph* gp, const int32_t* roots, int32_t num_roots, ss_semir
       unsigned long long* dpc =
           plan.counting ? g.ws.counters + plan.words_per_run * r + plan.lcap * kCountSlots * kCountFields
                         : nullptr;
+      const int32_t src = s == SS_TROPICAL ? kDpFromTropical : kDpFromRowD;
       if ((rc = launch_dp(g, g.ws, *plan.ul, plan.as, plan.unroll, plan.waves, plan.max_groups,
-                          dist_r, parent_r, st, dpc, e0, e1)))
+                          nullptr, src, real_val ? nullptr : dist_r, parent_r, st, dpc, e0, e1)))
         return rc;
     }
     if ((rc = mark_event(g, plan, log.next_ev, st, &log.ev_last[r]))) return rc;
@@ -1383,7 +1388,7 @@ int slimsell_dp_parents(ss_graph* gp, const int32_t* dist, int32_t num_roots, in
   if (W < ul->count && (rc = get_assignment(*ul, W, w, g.n_cu, &as, false))) return rc;
   for (int32_t r = 0; r < num_roots; ++r) {
     rc = launch_dp(g, g.ws, *ul, as, g.tune.unroll, g.tune.waves_per_group, g.tune.max_groups,
-                   dist + (int64_t)r * g.n, parent + (int64_t)r * g.n, st);
+                   dist + (int64_t)r * g.n, kDpFromDist, nullptr, parent + (int64_t)r * g.n, st);
     if (rc) return rc;
   }
   return SS_OK;
@@ -1571,11 +1576,15 @@ int slimsell_bfs_noalloc(ss_graph* gp, const int32_t* roots, int32_t num_roots, 
     if (o->iterations_out) o->iterations_out[r] = log.iters[r];
     int32_t* dist_r = dist + (int64_t)r * g.n;
     int32_t* parent_r = parent ? parent + (int64_t)r * g.n : nullptr;
-    rc = launch_finalise(s, g, w, dist_r, s == SS_SELMAX ? parent_r : nullptr,
-                         real_val ? real_val + (int64_t)r * g.n : nullptr, st);
-    if (rc) return rc;
+    // with the DP transformation, its last pass writes the distances too
+    if (!dp || real_val) {
+      rc = launch_finalise(s, g, w, dist_r, s == SS_SELMAX ? parent_r : nullptr,
+                           real_val ? real_val + (int64_t)r * g.n : nullptr, st);
+      if (rc) return rc;
+    }
     if (dp && (rc = launch_dp(g, w, *plan.ul, plan.as, plan.unroll, plan.waves, plan.max_groups,
-                              dist_r, parent_r, st)))
+                              nullptr, s == SS_TROPICAL ? kDpFromTropical : kDpFromRowD,
+                              real_val ? nullptr : dist_r, parent_r, st)))
       return rc;
   }
   return SS_OK;

@@ -338,10 +338,16 @@ int launch_sched_level(int semiring, int waves, int unroll, int64_t max_groups,
 // counts its chunks and cells; ev_begin/ev_end (hipEvent_t or NULL) bracket
 // the sweep kernel.
 // `as` (or NULL: round-robin) is the units' per-wavefront assignment for
-// the sweep's grid.
+// the sweep's grid.  `src` says where the row-order distances come from:
+// kDpFromDist gathers the original-order `dist`; right after a BFS on ws,
+// kDpFromTropical reads its tropical distance vector (ws.state) and
+// kDpFromRowD the distances the real and boolean forms keep in ws.d; with
+// those two, `dist_out` (or NULL) receives the run's distances in original
+// order, written by the pass that writes the parents.
+constexpr int32_t kDpFromDist = 0, kDpFromTropical = 1, kDpFromRowD = 2;
 int launch_dp(const Graph& g, const Workspace& ws, const UnitList& ul,
               const UnitList::Assignment* as, int unroll, int waves, int64_t max_groups,
-              const int32_t* dist, int32_t* parent, void* stream,
+              const int32_t* dist, int32_t src, int32_t* dist_out, int32_t* parent, void* stream,
               unsigned long long* counters = nullptr, void* ev_begin = nullptr,
               void* ev_end = nullptr);
 int launch_sched_init(const Graph& g, const Workspace& ws, int32_t root_row, void* stream);
