@@ -1576,7 +1576,7 @@ __global__ void init_kernel(int32_t n, int32_t n_pad, int64_t n_chunks, const in
     return;
   }
   d[r] = root ? 0 : -1;
-  g[r] = (root || phantom) ? 0 : 1;
+  if (SEMI != SS_SELMAX) g[r] = (root || phantom) ? 0 : 1;  // sel-max reads no filter
   if (SEMI == SS_REAL) {
     static_cast<float*>(va)[r] = root ? 1.0f : 0.0f;
     static_cast<float*>(vb)[r] = 0.0f;

@@ -86,3 +86,31 @@ def test_dp_on_batched_distances_and_edge_cases(ss):
     with pytest.raises(ValueError):
         G.dp_parents(torch.zeros(G.n + 1, dtype=torch.int32, device="cuda"))
     G.close()
+
+
+@pytest.mark.parametrize("no_alloc", [False, True], ids=["bfs", "noalloc"])
+def test_dp_pass_writes_every_distance_and_parent(ss, no_alloc):
+    """Without real values, the transformation's last pass writes the
+    distances as well as the parents: outputs filled with garbage first must
+    come back whole and equal to the oracle's, for every semiring that needs
+    the transformation, on a graph with isolated and unreachable vertices."""
+    import torch
+    e = graphgen.er(5000, 9000, seed=76)
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e)
+    roots = graphgen.pick_roots(e, 3, seed=77)
+    exs = [oracle.expected(g, int(r)) for r in roots]
+    try:
+        for semi in ("tropical", "real", "boolean"):
+            note("garbage-filled outputs", semi, "noalloc" if no_alloc else "bfs")
+            dist = torch.full((len(roots), G.n), -7, dtype=torch.int32, device="cuda")
+            parent = torch.full_like(dist, -7)
+            res = G.bfs(roots, semi, dp=True, want_real=False, dist=dist, parent=parent,
+                        no_alloc=no_alloc)
+            torch.cuda.synchronize()
+            assert res.real_val is None
+            for i, ex in enumerate(exs):
+                np.testing.assert_array_equal(dist[i].cpu().numpy(), ex.dist)
+                np.testing.assert_array_equal(parent[i].cpu().numpy(), ex.parent)
+    finally:
+        G.close()
