@@ -296,6 +296,14 @@ typedef struct {
  * bits).  This flag turns the summary off (every term outside the staged
  * prefix is read).  Runs with a schedule never use it. */
 #define SS_NO_SUMMARY 32
+/* Learned schedule: every workgroup of a level stages the model only once
+ * the level's features lie within tau of an anchor of the model's training
+ * domain, one memory round trip later, instead of while it reads the
+ * counters.  Without this flag a graph's learned runs choose by themselves:
+ * up front on the first run and after any run with a level inside the
+ * domain, only inside the domain after a run with none.  The decisions are
+ * the same either way; only their cost differs. */
+#define SS_SCHED_LAZY 64
 
 /*
  * Per-call options.  Zero-initialise, set size = sizeof(ss_bfs_opts).
@@ -332,7 +340,8 @@ typedef struct {
  *   iterations_out  : host int32[num_roots] or NULL: SpMV iterations per root
  *                     (eccentricity + 1; the last one discovers nothing).
  *   flags           : SS_STATS_TIME, SS_STATS_TIME_BFS, SS_STATS_COUNTERS,
- *                     SS_RUN_PERSISTENT, SS_SELL_VAL, SS_NO_SUMMARY.
+ *                     SS_RUN_PERSISTENT, SS_SELL_VAL, SS_NO_SUMMARY,
+ *                     SS_SCHED_LAZY.
  *   level_cap       : levels per root recorded in level_stats_out.
  *   level_stats_out : host ss_level_stats[num_roots * level_cap] or NULL;
  *                     entry [r * level_cap + k - 1] describes level k of root r.

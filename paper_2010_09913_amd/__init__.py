@@ -219,13 +219,16 @@ class Graph:
             level_cap: int = 0, timing: bool = False, counters: bool = None,
             persistent: bool = False, want_parent: bool = True, want_real: bool = True,
             dp: bool = False, sell: bool = False, summary: bool = True, dist=None,
-            parent=None, real_val=None, no_alloc: bool = False) -> BfsResult:
+            parent=None, real_val=None, no_alloc: bool = False,
+            sched_lazy: bool = False) -> BfsResult:
         """BFS from every root; outputs are device tensors in original vertex IDs.
 
         Sel-max returns parents (unless want_parent=False); dp=True gives the
         other semirings parents too, by the DP transformation after each BFS.
         sell=True runs the Sell-C-sigma comparator (a val array beside col).
         summary=False turns off the frontier-summary filter of the gathers.
+        sched_lazy=True makes the learned schedule stage its model only for
+        levels inside the model's domain (SS_SCHED_LAZY).
         level_cap > 0 records per-level statistics (fused counters unless
         counters=False); timing=True adds event timings per level and per root,
         timing="bfs" per root only.  no_alloc=True calls the allocation-free
@@ -265,7 +268,8 @@ class Graph:
             _native.SS_STATS_COUNTERS if counters else 0) | (
             _native.SS_RUN_PERSISTENT if persistent else 0) | (
             _native.SS_SELL_VAL if sell else 0) | (
-            0 if summary else _native.SS_NO_SUMMARY)
+            0 if summary else _native.SS_NO_SUMMARY) | (
+            _native.SS_SCHED_LAZY if sched_lazy else 0)
         lvl = runs = None
         if level_cap > 0:
             lvl = (_native.LevelStats * (nr * level_cap))()

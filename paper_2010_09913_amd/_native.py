@@ -89,6 +89,7 @@ SS_RUN_PERSISTENT = 4
 SS_SELL_VAL = 8
 SS_STATS_TIME_BFS = 16
 SS_NO_SUMMARY = 32
+SS_SCHED_LAZY = 64
 
 
 class BfsOpts(ctypes.Structure):

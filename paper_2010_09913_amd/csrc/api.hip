@@ -386,10 +386,11 @@ static int alloc_workspace(Graph& g) {
     ws.summ_words = (int32_t)summ_words;
   }
   void* h = nullptr;
-  hipError_t e = hipHostMalloc(&h, sizeof(uint64_t) * kRing,
+  hipError_t e = hipHostMalloc(&h, sizeof(uint64_t) * (kRing + 1),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(report ring)");
   std::memset(h, 0, sizeof(uint64_t) * kRing);
+  static_cast<uint64_t*>(h)[kRing] = 1;  // a graph's first learned run stages its model up front
   ws.h_report = static_cast<volatile uint64_t*>(h);
   void* dptr = nullptr;
   SS_HIP(hipHostGetDevicePointer(&dptr, h, 0));
@@ -450,6 +451,7 @@ struct RunPlan {
   int32_t prefix_words = 0;   // summary words covering the chunks of the LDS prefix
   int32_t slimwork = 2;
   int32_t schedule = 0;
+  bool sched_lazy = false;    // the learned schedule stages its model only inside the box
   uint32_t lds_bytes = 0;
   UnitList* ul = nullptr;
   const UnitList::Assignment* as = nullptr;  // per-wavefront units of the level launch
@@ -499,8 +501,9 @@ static int plan_run(Graph& g, const ss_bfs_opts* o, int policy, int32_t runs,
   if (o->level_cap < 0) return set_error(SS_EINVAL, "level_cap < 0");
   if (o->flags &
       ~(SS_STATS_TIME | SS_STATS_COUNTERS | SS_RUN_PERSISTENT | SS_SELL_VAL | SS_STATS_TIME_BFS |
-        SS_NO_SUMMARY))
+        SS_NO_SUMMARY | SS_SCHED_LAZY))
     return set_error(SS_EINVAL, "bad flags");
+  p->sched_lazy = (o->flags & SS_SCHED_LAZY) != 0;
   p->persistent = (o->flags & SS_RUN_PERSISTENT) != 0;
   p->sell = (o->flags & SS_SELL_VAL) != 0;
   if (p->sell && (p->persistent || o->schedule || policy == kBatchSemiring))
@@ -701,6 +704,17 @@ static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
   sl.report = g.ws.d_report;
   sl.variant = g.ws.variant;
   sl.decided = g.ws.decided;
+  // The learned schedule stages its model in every workgroup before it
+  // knows whether the level needs it; on a graph whose levels all fell
+  // outside the model's domain last time, it stages it only for a level
+  // inside the domain.  The word is read and cleared between runs: the
+  // levels of the previous run have all finished by then (the host saw its
+  // last report).
+  if (p.schedule == 1 && p.has_model) {
+    sl.eager = (!p.sched_lazy && g.ws.h_report[kRing] != 0) ? 1 : 0;
+    g.ws.h_report[kRing] = 0;
+    sl.in_box = g.ws.d_report + kRing;
+  }
   sl.qn = g.ws.qn;
   sl.seg_n = g.ws.seg_n;
   sl.ring_ctr = g.ws.ring_ctr;

@@ -128,6 +128,8 @@ struct Workspace {
   uint32_t* summ = nullptr;
   int32_t summ_words = 0;
   // host-mapped report ring written by the GPU: (tag << 1) | found
+  // [kRing] level reports, then one word the learned schedule sets when its
+  // model decides a level of the run (the level lies in its domain)
   volatile uint64_t* h_report = nullptr;
   uint64_t* d_report = nullptr;  // device view of h_report
 };
@@ -294,6 +296,8 @@ struct SchedLaunch {
   const float* anchors;   // training-domain anchors [n_anchors][6] or nullptr
   const float* box;       // [12] their box widened by tau (lower, upper) or nullptr
   uint64_t* decided;      // [kRing] decisions published for later workgroup rounds
+  uint64_t* in_box;       // device view of the host word "the model decided a level"
+  int32_t eager;          // stage the model up front (the last learned run used it)
   int32_t n_anchors;
   float tau2;             // squared distance beyond which the heuristic decides
   float* log;

@@ -1197,6 +1197,8 @@ struct SchedArgs {
   const float* anchors;   // the model's training domain [n_anchors][6], or nullptr
   const float* box;       // [12] the anchors' box widened by tau: lower, then upper bounds
   uint64_t* decided;      // [kRing] published decisions (tag << 3 | variant + 2), or nullptr
+  uint64_t* in_box;       // host-visible word: set when the model decides a level, or nullptr
+  int32_t eager;          // stage the model before the domain test (else only inside the domain)
   int32_t n_anchors;
   float tau2;             // squared distance to the nearest anchor the model may answer at
   float* log;             // [log_cap * 12]
@@ -1245,10 +1247,14 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   // workgroup, and each thread holds one anchor of the training domain, in
   // the same round of loads as the counters below, so scoring a level costs
   // no global-memory round trip of its own.
-  const bool staged = (s.mode == 1) && s.model;
+  // Where no level of the last learned run on this graph was inside the
+  // model's domain (`eager` clear), the box and anchors are staged up front
+  // and the model only for a level inside the domain.
+  const bool learned = (s.mode == 1) && s.model;
+  const bool eager = learned && s.eager;
   float anc[kFeatures];
-  const bool has_anc = staged && s.anchors && t < s.n_anchors;
-  if (staged) {
+  const bool has_anc = learned && s.anchors && t < s.n_anchors;
+  auto stage_model = [&]() {
     // (the second layer's weights transposed, so that lane u reading weight
     // (u, j) of every hidden unit u at once touches consecutive words)
     constexpr int kW2 = 32 * kFeatures + 32;
@@ -1256,12 +1262,13 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       const int q = i - kW2;
       sh.w[(q >= 0 && q < 32 * 32) ? kW2 + (q & 31) * 32 + (q >> 5) : i] = s.model[i];
     }
-    if (s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
-    if (has_anc) {
+  };
+  if (learned && s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
+  if (has_anc) {
 #pragma unroll
-      for (int f = 0; f < kFeatures; ++f) anc[f] = s.anchors[t * kFeatures + f];
-    }
+    for (int f = 0; f < kFeatures; ++f) anc[f] = s.anchors[t * kFeatures + f];
   }
+  if (eager) stage_model();
   // Level k-1's counters: written by earlier kernels (or, in the persistent
   // form, before the grid barrier, whose acquire makes them visible), so
   // plain loads see them.  The lanes of the first wavefront load one slot
@@ -1329,7 +1336,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   // every thread measures its anchor's distance to the level's features and
   // the nearest decides.  Only then does the first wavefront score the four
   // variants with the MLP, one hidden unit per lane, in registers.
-  bool use_model = staged;
+  bool use_model = learned;
   if (use_model && s.anchors && s.box) {
     bool in = true;
     for (int f = 0; f < kFeatures; ++f)
@@ -1362,6 +1369,14 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     use_model = __syncthreads_or(near ? 1 : 0) != 0;
   }
   if (use_model) {
+    // inside the domain: tell the host to stage up front on the next run,
+    // and stage now if this run does not
+    if (writer && t == 0 && s.in_box)
+      __hip_atomic_store(s.in_box, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (!eager) {
+      stage_model();
+      __syncthreads();
+    }
     if (t < kC) {
       const float* W1 = sh.w;
       const float* b1 = W1 + 32 * kFeatures;
@@ -1808,6 +1823,8 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.anchors = p.anchors;
   s.box = p.box;
   s.decided = p.decided;
+  s.in_box = p.in_box;
+  s.eager = p.eager;
   s.n_anchors = p.n_anchors;
   s.tau2 = p.tau2;
   s.log = p.log;

@@ -207,3 +207,48 @@ def test_training_domain_decides_between_model_and_heuristic(ss):
             ss.sched_load(np.concatenate([w, bad, np.zeros(6)]).astype(np.float32))
     ss.sched_clear()
     G.close()
+
+
+def test_model_staged_inside_the_box_decides_the_same(ss):
+    """The learned schedule decides identically whether the model is staged
+    before the domain test (a graph's first learned run, or after a run with
+    some level inside the domain) or only for levels inside the domain
+    (forced, or by itself after a run with none): same outputs and the same
+    log (features, scores, variants) bit for bit, per-level and persistent."""
+    e = _graphs()["rmat"]
+    g = oracle.csr_from_edgelist(e)
+    G = ss.Graph.from_edgelist(e)
+    rng = np.random.default_rng(7)
+    w = rng.normal(0, 0.5, mlp.PARAMS).astype(np.float32)
+    root = int(graphgen.pick_roots(e, 1, seed=47)[0])
+    ex = oracle.expected(g, root)
+    it = ex.iterations
+    feats = mlp.features(ex.dist, g.degree, g.n, g.entries).astype(np.float32)
+
+    def run(model, **kw):
+        import torch
+        ss.sched_load(model)
+        res = G.bfs([root], "selmax", schedule="learned", level_cap=4096, **kw)
+        torch.cuda.synchronize()
+        _check(res, ex, "selmax")
+        return res.levels["variant"][0][:it].copy(), G.sched_log(it)
+
+    try:
+        for name, anchors, tau in (("inside", feats, 1e-3), ("mixed", feats[::2], 1e-3),
+                                   ("outside", feats + 5.0, 0.5)):
+            note("staging", name)
+            model = np.concatenate([w, [tau, len(anchors)], anchors.ravel()]).astype(np.float32)
+            v_eager, log_eager = run(model)                   # up front (default)
+            v_lazy, log_lazy = run(model, sched_lazy=True)    # only inside the box
+            np.testing.assert_array_equal(v_lazy, v_eager)
+            np.testing.assert_array_equal(log_lazy, log_eager)
+            # after the forced run the graph chooses by itself again; the
+            # persistent form decides the same as well
+            v_auto, log_auto = run(model)
+            np.testing.assert_array_equal(v_auto, v_eager)
+            np.testing.assert_array_equal(log_auto, log_eager)
+            v_p, _ = run(model, persistent=True, sched_lazy=True)
+            np.testing.assert_array_equal(v_p, v_eager)
+    finally:
+        ss.sched_clear()
+        G.close()
