@@ -722,6 +722,7 @@ static SchedLaunch sched_launch(const Graph& g, const RunPlan& p) {
   sl.model = p.has_model ? g.ws.model : nullptr;
   sl.anchors = p.n_anchors ? g.ws.model + kModelSize + 2 : nullptr;
   sl.box = p.n_anchors ? g.ws.model + kModelSize + 2 + (int64_t)p.n_anchors * kFeatures : nullptr;
+  sl.cells = sl.box ? sl.box + 2 * kFeatures : nullptr;
   sl.n_anchors = p.n_anchors;
   sl.tau2 = p.tau * p.tau;
   sl.log = g.ws.sched_log;
@@ -1098,6 +1099,41 @@ int slimsell_sched_load(const float* w, int64_t count) {
     }
     m.insert(m.end(), lo, lo + kFeatures);
     m.insert(m.end(), hi, hi + kFeatures);
+    // the cell map: a level's cell is floor((x - lo) * scale) per feature,
+    // clamped to the bins, in single precision on the device; the cells an
+    // anchor's cube touches are taken a thousandth of a bin wider on each
+    // side, so no rounding of that product can put a level within tau of
+    // the anchor into a cell left clear
+    float scale[kFeatures];
+    for (int f = 0; f < kFeatures; ++f) scale[f] = (float)kCellBins / (hi[f] - lo[f]);
+    uint32_t bits[kCellWords] = {};
+    for (int64_t a = 0; a < K; ++a) {
+      int b0[kFeatures], b1[kFeatures];
+      for (int f = 0; f < kFeatures; ++f) {
+        const double x = w[kModelSize + 2 + a * kFeatures + f];
+        const double r = (double)tau * 1.001 + 1e-6 * std::max(std::fabs(lo[f]), std::fabs(hi[f]));
+        const double u0 = (x - r - lo[f]) * scale[f] - 1e-3, u1 = (x + r - lo[f]) * scale[f] + 1e-3;
+        b0[f] = (int)std::min<double>(std::max<double>(std::floor(u0), 0.0), kCellBins - 1);
+        b1[f] = (int)std::min<double>(std::max<double>(std::floor(u1), 0.0), kCellBins - 1);
+      }
+      int q[kFeatures];
+      for (int f = 0; f < kFeatures; ++f) q[f] = b0[f];
+      for (;;) {  // every cell of the product of the ranges
+        int idx = 0;
+        for (int f = kFeatures - 1; f >= 0; --f) idx = idx * kCellBins + q[f];
+        bits[idx >> 5] |= 1u << (idx & 31);
+        int f = 0;
+        while (f < kFeatures && q[f] == b1[f]) q[f] = b0[f], ++f;
+        if (f == kFeatures) break;
+        ++q[f];
+      }
+    }
+    m.insert(m.end(), scale, scale + kFeatures);
+    for (int i = 0; i < kCellWords; ++i) {
+      float v;
+      std::memcpy(&v, &bits[i], sizeof(v));  // the words travel as raw bits
+      m.push_back(v);
+    }
   }
   std::lock_guard<std::mutex> lk(g_model_mu);
   g_model.swap(m);

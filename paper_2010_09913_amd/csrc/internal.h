@@ -171,9 +171,16 @@ constexpr int kFeatures = 6;
 // back to the fixed heuristic.  The library appends the anchors' bounding box
 // widened by tau (6 lower, then 6 upper bounds): a level outside it is
 // farther than tau from every anchor, which settles the test without the
-// model or the anchor scan.
+// model or the anchor scan.  Then a coarse map of the box: kCellBins bins per
+// feature (6 scales: bins per unit of each feature), and one bit per cell,
+// set where the cell meets some anchor's cube of half-width tau (plus the
+// box's margin).  A level in a clear cell is farther than tau from every
+// anchor too.
 constexpr int kMaxAnchors = 1024;
-constexpr int kModelCap = kModelSize + 2 + kMaxAnchors * kFeatures + 2 * kFeatures;
+constexpr int kCellBins = 4;
+constexpr int kCellWords = 4096 / 32;  // kCellBins^6 bits
+constexpr int kModelCap =
+    kModelSize + 2 + kMaxAnchors * kFeatures + 2 * kFeatures + kFeatures + kCellWords;
 constexpr int kRing = 1024;  // level tags / reports are kept in rings of this size
 
 struct Graph {
@@ -295,6 +302,7 @@ struct SchedLaunch {
   const float* model;
   const float* anchors;   // training-domain anchors [n_anchors][6] or nullptr
   const float* box;       // [12] their box widened by tau (lower, upper) or nullptr
+  const float* cells;     // [6 + kCellWords] the box's cell map (scales, bits) or nullptr
   uint64_t* decided;      // [kRing] decisions published for later workgroup rounds
   uint64_t* in_box;       // device view of the host word "the model decided a level"
   int32_t eager;          // stage the model up front (the last learned run used it)

@@ -1196,6 +1196,7 @@ struct SchedArgs {
   const float* model;     // nullptr = no model
   const float* anchors;   // the model's training domain [n_anchors][6], or nullptr
   const float* box;       // [12] the anchors' box widened by tau: lower, then upper bounds
+  const float* cells;     // [6] bins per unit of each feature, then kCellWords bit words
   uint64_t* decided;      // [kRing] published decisions (tag << 3 | variant + 2), or nullptr
   uint64_t* in_box;       // host-visible word: set when the model decides a level, or nullptr
   int32_t eager;          // stage the model before the domain test (else only inside the domain)
@@ -1215,6 +1216,8 @@ struct SchedArgs {
 struct SchedShared {
   float w[kModelSize];         // the model's parameters, staged once per level
   float box[2 * kFeatures];    // the training domain's box (lower, upper)
+  float cscale[kFeatures];     // the box's cell map: bins per unit of each feature
+  uint32_t cells[kCellWords];  // and one bit per cell (set: near some anchor)
   float x[kFeatures], out[kVariants];
   double sums[3];
   float mf, mu;
@@ -1248,8 +1251,9 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   // the same round of loads as the counters below, so scoring a level costs
   // no global-memory round trip of its own.
   // Where no level of the last learned run on this graph was inside the
-  // model's domain (`eager` clear), the box and anchors are staged up front
-  // and the model only for a level inside the domain.
+  // model's domain (`eager` clear), only the box and its cell map are staged
+  // up front, and the model and anchors only for a level in a cell near
+  // some anchor.
   const bool learned = (s.mode == 1) && s.model;
   const bool eager = learned && s.eager;
   float anc[kFeatures];
@@ -1262,11 +1266,17 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
       const int q = i - kW2;
       sh.w[(q >= 0 && q < 32 * 32) ? kW2 + (q & 31) * 32 + (q >> 5) : i] = s.model[i];
     }
-  };
-  if (learned && s.box && t < 2 * kFeatures) sh.box[t] = s.box[t];
-  if (has_anc) {
+    if (has_anc) {
 #pragma unroll
-    for (int f = 0; f < kFeatures; ++f) anc[f] = s.anchors[t * kFeatures + f];
+      for (int f = 0; f < kFeatures; ++f) anc[f] = s.anchors[t * kFeatures + f];
+    }
+  };
+  if (learned && s.box) {
+    for (int i = t; i < 3 * kFeatures + kCellWords; i += blockDim.x) {
+      if (i < 2 * kFeatures) sh.box[i] = s.box[i];
+      else if (i < 3 * kFeatures) sh.cscale[i - 2 * kFeatures] = s.cells[i - 2 * kFeatures];
+      else sh.cells[i - 3 * kFeatures] = __float_as_uint(s.cells[i - 2 * kFeatures]);
+    }
   }
   if (eager) stage_model();
   // Level k-1's counters: written by earlier kernels (or, in the persistent
@@ -1312,7 +1322,7 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   }
   // the anchors are needed in registers from here on: without this the
   // compiler issues their loads only where they are used, after the barrier
-  if (has_anc) {
+  if (eager && has_anc) {
 #pragma unroll
     for (int f = 0; f < kFeatures; ++f) asm volatile("" ::"v"(anc[f]));
   }
@@ -1339,9 +1349,22 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
   bool use_model = learned;
   if (use_model && s.anchors && s.box) {
     bool in = true;
-    for (int f = 0; f < kFeatures; ++f)
+    int cell = 0, stride = 1;
+    for (int f = 0; f < kFeatures; ++f) {
       in = in && sh.x[f] >= sh.box[f] && sh.x[f] <= sh.box[kFeatures + f];
+      const int q = (int)fminf(fmaxf(floorf((sh.x[f] - sh.box[f]) * sh.cscale[f]), 0.0f),
+                               (float)(kCellBins - 1));
+      cell += q * stride;
+      stride *= kCellBins;
+    }
+    // inside the box, a level in a cell that meets no anchor's cube is
+    // outside the domain as well
+    in = in && ((sh.cells[cell >> 5] >> (cell & 31)) & 1u) != 0u;
     use_model = in;  // the same value in every thread
+  }
+  if (use_model && !eager) {
+    stage_model();
+    if (!s.anchors) __syncthreads();  // (otherwise the anchor test's barrier)
   }
   if (use_model && s.anchors) {
     // inside the domain iff some anchor lies within tau: each thread tests
@@ -1369,14 +1392,9 @@ __device__ int32_t schedule_pick(const SchedArgs& s, int32_t k, SchedShared& sh,
     use_model = __syncthreads_or(near ? 1 : 0) != 0;
   }
   if (use_model) {
-    // inside the domain: tell the host to stage up front on the next run,
-    // and stage now if this run does not
+    // inside the domain: tell the host to stage up front on the next run
     if (writer && t == 0 && s.in_box)
       __hip_atomic_store(s.in_box, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (!eager) {
-      stage_model();
-      __syncthreads();
-    }
     if (t < kC) {
       const float* W1 = sh.w;
       const float* b1 = W1 + 32 * kFeatures;
@@ -1822,6 +1840,7 @@ static SchedArgs sched_args(const SchedLaunch& p, int32_t level, uint32_t run_id
   s.model = p.model;
   s.anchors = p.anchors;
   s.box = p.box;
+  s.cells = p.cells;
   s.decided = p.decided;
   s.in_box = p.in_box;
   s.eager = p.eager;
