@@ -164,6 +164,11 @@ def test_model_that_prefers_one_variant_and_nan_fallback(ss):
     G.close()
 
 
+def _offsets(rng, shape, length):
+    d = rng.normal(size=shape)
+    return (length * d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+
+
 def test_training_domain_decides_between_model_and_heuristic(ss):
     e = _graphs()["rmat"]
     g = oracle.csr_from_edgelist(e)
@@ -182,6 +187,10 @@ def test_training_domain_decides_between_model_and_heuristic(ss):
             "outside": (feats + 5.0, 0.5),
             # every other level is an anchor, tau below the gaps: mixed
             "mixed": (feats[::2], 1e-3),
+            # every level half of tau from its anchor in a random direction:
+            # inside, though level and anchor may sit in different cells of
+            # the domain box's map, which must not clear the level's cell
+            "near": (feats + _offsets(rng, feats.shape, 0.5 * 0.05), 0.05),
         }
         for name, (anchors, tau) in cases.items():
             note("domain", root, name)
