@@ -1473,8 +1473,8 @@ __device__ __forceinline__ void sched_clear_level(const SchedArgs& s, int32_t k)
 // what level k+1 accumulates into.  The running totals are double-buffered
 // by level parity: level k reads buffer (k-1)&1 and writes buffer k&1.
 template <class S, int U, bool STAGED>
-__global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
-  extern __shared__ uint8_t lds_stage[];
+__device__ __forceinline__ void sched_level_entry(const LevelArgs& a, const SchedArgs& s,
+                                                  uint8_t* lds_stage) {
   __shared__ SchedShared sh;
   const int32_t k = a.level;
   const bool writer = blockIdx.x == 0;
@@ -1496,6 +1496,20 @@ __global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
                              a.varrive2[v], a.vpiece_cols[v], a.vwave_off[v], lds_stage);
   else
     push_scatter_body<S>(a, grid_wave(), grid_waves(), push_stage<STAGED>(a, lds_stage));
+}
+
+template <class S, int U, bool STAGED>
+__global__ void sched_level_kernel(LevelArgs a, SchedArgs s) {
+  extern __shared__ uint8_t lds_stage[];
+  sched_level_entry<S, U, STAGED>(a, s, lds_stage);
+}
+
+// The four-column form held to 64 registers per lane, as for plain levels:
+// two 16-wavefront workgroups per compute unit.
+template <class S, bool STAGED>
+__global__ void __launch_bounds__(1024, 8) sched_level_kernel_w8(LevelArgs a, SchedArgs s) {
+  extern __shared__ uint8_t lds_stage[];
+  sched_level_entry<S, 4, STAGED>(a, s, lds_stage);
 }
 
 // Level-0 state of a scheduled run: the root is the frontier queue, and the
@@ -1863,7 +1877,7 @@ static void launch_sched_level_u(int waves, int unroll, unsigned grid, const Lev
                                  const SchedArgs& sa, hipStream_t st) {
   const size_t lds = STAGED ? level_lds(a) : 0;
   if (unroll == 4)
-    sched_level_kernel<S, 4, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
+    sched_level_kernel_w8<S, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
   else if (unroll == 16)
     sched_level_kernel<S, 16, STAGED><<<grid, waves * kC, lds, st>>>(a, sa);
   else
